@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs (numpy, float64).  No multigrid arithmetic lives here.
+
+Shared by the tests (for the GPU path and the CPU oracle alike) and the benchmark.
+Arrays hold all n^d nodes of the unit square/cube including the boundary, C order
+[z][y][x]; node i sits at x_i = i/(n-1).
+
+Inputs of the paper's model problem (Sect. 5): a right-hand side f on [0,1]^d and
+Dirichlet data; the five workloads of this project:
+  1  2D, 129^2, f = 2 pi^2 sin(pi x) sin(pi y)
+  2  3D, 257^3, f = 3 pi^2 sin sin sin + 0.1 * U[-1,1]   (seed 2)
+  3  3D, 513^3, f = U[-1,1]                               (seed 3)
+  4  3D, 257^3, k = exp(GRF), f = 1, k_obs = k exp(0.1 GRF')  (seeds 4, 104)
+  5  3D, 513^3, as 4                                      (seeds 5, 105)
+Random values are drawn with numpy.random.default_rng(seed) (PCG64) over the interior
+block in C order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def coords(n: int) -> np.ndarray:
+    return np.arange(n, dtype=np.float64) / (n - 1)
+
+
+def interior(dim: int):
+    return (slice(1, -1),) * dim
+
+
+def manufactured_u(dim: int, n: int) -> np.ndarray:
+    """u = prod_a sin(pi x_a) sampled at the nodes."""
+    s = np.sin(np.pi * coords(n))
+    if dim == 2:
+        return np.multiply.outer(s, s)
+    return np.multiply.outer(np.multiply.outer(s, s), s)
+
+
+def manufactured_f(dim: int, n: int) -> np.ndarray:
+    """f = -Laplace(prod sin(pi x_a)) = d pi^2 prod sin(pi x_a) (continuous Laplacian) on
+    interior nodes, 0 on the boundary."""
+    f = dim * np.pi ** 2 * manufactured_u(dim, n)
+    out = np.zeros_like(f)
+    out[interior(dim)] = f[interior(dim)]
+    return out
+
+
+def uniform_interior(dim: int, n: int, seed: int, amplitude: float = 1.0) -> np.ndarray:
+    """amplitude * U[-1,1] iid on interior nodes, 0 on the boundary."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((n,) * dim)
+    out[interior(dim)] = amplitude * rng.uniform(-1.0, 1.0, size=(n - 2,) * dim)
+    return out
+
+
+def constant_interior(dim: int, n: int, value: float = 1.0) -> np.ndarray:
+    out = np.zeros((n,) * dim)
+    out[interior(dim)] = value
+    return out
+
+
+def harmonic_dirichlet(n: int) -> np.ndarray:
+    """The paper's 3D benchmark data (Sect. 5, Eq. 2): u = sin(pi x) sin(pi y) sinh(sqrt2 pi z),
+    a harmonic function (f = 0); returned on all nodes (boundary = Dirichlet data)."""
+    x = coords(n)
+    sx = np.sin(np.pi * x)
+    sz = np.sinh(np.sqrt(2.0) * np.pi * x)
+    # index order [z][y][x]
+    return np.multiply.outer(sz, np.multiply.outer(sx, sx))
+
+
+def gaussian_random_field(dim: int, n: int, seed: int, corr: float = 0.1,
+                          sigma: float = 1.0) -> np.ndarray:
+    """Stationary Gaussian field with covariance sigma^2 exp(-r^2 / (2 corr^2)).
+
+    White noise N(0,1) on a periodic box [-1/2, 3/2)^d with spacing H = max(1/(n-1), 1/128)
+    is filtered in Fourier space by the square root of the covariance's spectrum and
+    normalised by the filter's theoretical variance (not the sample's); the box is 2 wide so
+    the periodic wrap lies >= 5 correlation lengths from [0,1]^d.  Nodes of the n-grid that
+    are not nodes of the H-grid take (multi)linear interpolation of it.
+    """
+    H = max(1.0 / (n - 1), 1.0 / 128)
+    m = int(round(2.0 / H))
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(size=(m,) * dim)
+    kk = 2.0 * np.pi * np.fft.fftfreq(m, d=H)
+    k2 = np.zeros((m,) * dim)
+    for a in range(dim):
+        shape = [1] * dim
+        shape[a] = m
+        k2 = k2 + (kk ** 2).reshape(shape)
+    amp = np.exp(-0.25 * corr ** 2 * k2)  # sqrt of the Gaussian spectrum
+    g = np.real(np.fft.ifftn(np.fft.fftn(w) * amp))
+    g *= sigma / np.sqrt(np.mean(amp ** 2))
+    # window [0, 1] of the box: H-grid indices m/4 .. 3m/4
+    lo = m // 4
+    g = g[(slice(lo, lo + m // 2 + 1),) * dim]
+    ratio = int(round((n - 1) * H))  # n-grid steps per H-grid step (a power of two)
+    if ratio > 1:
+        pos = np.arange(n, dtype=np.float64) / ratio  # node i of the n-grid in H-grid units
+        i0 = np.minimum(np.floor(pos).astype(np.int64), g.shape[0] - 2)
+        t = pos - i0
+        for a in range(dim):
+            shape = [1] * dim
+            shape[a] = n
+            tt = t.reshape(shape)
+            g = (1.0 - tt) * np.take(g, i0, axis=a) + tt * np.take(g, i0 + 1, axis=a)
+    return np.ascontiguousarray(g)
+
+
+def lognormal_k(dim: int, n: int, seed: int) -> np.ndarray:
+    return np.exp(gaussian_random_field(dim, n, seed))
+
+
+def config(idx: int) -> dict:
+    """Inputs of workload idx (1..5) as numpy arrays plus their description."""
+    if idx == 1:
+        n, dim, levels = 129, 2, 6
+        return dict(dim=dim, n=n, levels=levels, f=manufactured_f(dim, n), k=None)
+    if idx == 2:
+        n, dim, levels = 257, 3, 8
+        f = manufactured_f(dim, n) + uniform_interior(dim, n, seed=2, amplitude=0.1)
+        return dict(dim=dim, n=n, levels=levels, f=f, k=None)
+    if idx == 3:
+        n, dim, levels = 513, 3, 9
+        return dict(dim=dim, n=n, levels=levels, f=uniform_interior(dim, n, seed=3), k=None)
+    if idx in (4, 5):
+        n, levels = (257, 8) if idx == 4 else (513, 9)
+        dim = 3
+        k = lognormal_k(dim, n, seed=idx)
+        k_obs = k * np.exp(0.1 * gaussian_random_field(dim, n, seed=100 + idx))
+        return dict(dim=dim, n=n, levels=levels, f=constant_interior(dim, n), k=k, k_obs=k_obs)
+    raise ValueError(idx)
