@@ -1,0 +1,233 @@
+"""Benchmark: multigrid solve time to a 1e-10 relative residual on a 513^3 grid.
+
+Workload: 3D Poisson, 7-point finite differences, 513^3 nodes (zero Dirichlet data),
+f = U[-1,1] on interior nodes (numpy default_rng(3)), V(2,2) red-black Gauss-Seidel,
+9 levels.  One step = one complete solve from u = 0 to ||f - A u|| <= 1e-10 ||f|| with
+FP32 V-cycles inside FP64 iterative refinement (the headline form); the plain FP64 solve
+of the same system is timed beside it.  Inputs are resident on the GPU before timing.
+
+Also reported:
+  - fine-level smoother throughput (GLUP/s) from 20 sweeps timed alone, and the roofline
+    of the fine-level FP64 smoother kernel: algorithmic bytes per launch (24 B per interior
+    node: read u, read f, write u, for the 2 sweeps one launch fuses) / average launch
+    duration from HIP events on the library's stream;
+  - HBM traffic per launch from rocprofv3 counters committed under profiles/ (null if
+    absent or taken on different kernel source);
+  - the CPU oracle on a bounded sample of the same workload (one FP64 V-cycle and one
+    residual norm, scaled by the FP64 cycle count).
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--n 513]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+SMOOTHER_KERNEL = "k_rbgs_tiled"
+SMOOTHER_SOURCE = os.path.join(ROOT, "paper_2403_08063_amd", "csrc", "mg_smooth_tiled.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rbgs_tiled_f64_513_traffic.json")
+
+
+def light_speed_glups(bandwidth_gbs: float, bytes_per_lup: float) -> float:
+    """The paper's light-speed model (Sect. 6): maximum lattice updates per second =
+    bandwidth / bytes per update."""
+    return bandwidth_gbs / bytes_per_lup
+
+
+def source_hash(path: str) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(interior_nodes: int):
+    """HBM bytes per launch of the FP64 fused smoother from committed rocprofv3 counters,
+    if they were taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_hash(SMOOTHER_SOURCE) or rec.get("n") is None:
+        return None
+    if (rec["n"] - 2) ** 3 != interior_nodes:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(f_np, levels, fp64_cycles):
+    import numpy as np
+
+    import oracle
+
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    oracle.build()
+    u = np.zeros_like(f_np)
+    t0 = time.perf_counter()
+    oracle.vcycle(f_np, u, levels)
+    r = oracle.residual(f_np, u)
+    oracle.interior_norm2(r)
+    t = time.perf_counter() - t0
+    return {
+        "value": round(t * fp64_cycles * 1e3, 1),
+        "unit": "ms",
+        "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
+        "kind": "oracle",
+        "sample": f"one FP64 V(2,2) cycle + one residual norm on the full {f_np.shape[0]}^3 "
+                  f"workload ({t:.2f} s), scaled by the FP64 cycle count ({fp64_cycles})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=513)
+    ap.add_argument("--levels", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
+              "multi-GPU path; see the sharding design in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2403_08063_amd import Multigrid, inputs
+
+    n = args.n
+    levels = args.levels or (n - 1).bit_length() - 1  # coarsest level 3^3
+    dev = torch.device("cuda:0")
+    f_np = inputs.uniform_interior(3, n, seed=3)
+    f = torch.from_numpy(f_np).to(dev)
+    print(f"bench: n={n} levels={levels} inputs on GPU", file=sys.stderr, flush=True)
+
+    mg64 = Multigrid(3, n, levels, precision="f64", device=dev)
+    mg32 = Multigrid(3, n, levels, precision="f32_ir", device=dev)
+    u64 = torch.zeros_like(f)
+    u32 = torch.zeros_like(f)
+
+    def solve(mg, u):
+        u.zero_()
+        _, info = mg.solve(f, u, tol=1e-10)
+        return info
+
+    for _ in range(args.warmup):
+        solve(mg32, u32)
+        solve(mg64, u64)
+    torch.cuda.synchronize()
+
+    def timed(mg, u, steps):
+        times, info = [], None
+        for _ in range(steps):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = mg.solve(f, u, tol=1e-10)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        return times, info
+
+    t32, info32 = timed(mg32, u32, args.steps)
+    print(f"bench: fp32-ir solve {np.median(t32):.2f} ms cycles={info32.cycles}",
+          file=sys.stderr, flush=True)
+    t64, info64 = timed(mg64, u64, args.steps)
+    print(f"bench: fp64 solve {np.median(t64):.2f} ms cycles={info64.cycles}",
+          file=sys.stderr, flush=True)
+    err = float((u32 - u64).abs().max() / u64.abs().max())
+
+    # fine-level smoother alone: 20 sweeps = 10 fused launches (FP64), on the same stream
+    interior = (n - 2) ** 3
+    us = u64.clone()
+    stream = mg64.stream
+    sweeps = 20
+    mg64.smooth(0, f, us, sweeps)  # warm
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    ms = []
+    for _ in range(reps):
+        ev0.record(stream)
+        mg64.smooth(0, f, us, sweeps)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    t_sweeps = float(np.median(ms))
+    glups64 = sweeps * interior / (t_sweeps * 1e-3) / 1e9
+    launches = sweeps // 2
+    t_launch = t_sweeps / launches
+    bytes_launch = 24 * interior
+    achieved = bytes_launch / (t_launch * 1e-3) / 1e9
+    # FP32 smoother (inside the refinement cycles)
+    f32 = f.float()
+    u32s = torch.zeros_like(f32)
+    mg32.smooth(0, f32, u32s, sweeps)
+    ms32 = []
+    for _ in range(reps):
+        ev0.record(stream)
+        mg32.smooth(0, f32, u32s, sweeps)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms32.append(ev0.elapsed_time(ev1))
+    glups32 = sweeps * interior / (float(np.median(ms32)) * 1e-3) / 1e9
+
+    traffic = measured_traffic(interior)
+    value = float(np.median(t32))
+    rec = {
+        "metric": "MG solve time to 1e-10 rel. residual at 513^3 (FP32 V(2,2) cycles in FP64 "
+                  "iterative refinement); smoother GLUPS vs HBM roofline",
+        "value": round(value, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(value, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D Poisson 7-point FD, {n}^3 nodes, zero Dirichlet BC, f = U[-1,1] "
+                        f"(seed 3), V(2,2) red-black GS, {levels} levels, FP32 cycles in FP64 "
+                        "iterative refinement vs plain FP64, tol 1e-10",
+            "n": n, "levels": levels, "tol": 1e-10,
+        },
+        "fp32ir_solve_ms": round(value, 3),
+        "fp64_solve_ms": round(float(np.median(t64)), 3),
+        "speedup_fp32ir_vs_fp64": round(float(np.median(t64)) / value, 3),
+        "cycles_fp32ir": info32.cycles,
+        "cycles_fp64": info64.cycles,
+        "relres_fp32ir": info32.relres,
+        "relres_fp64": info64.relres,
+        "err_fp32ir_vs_fp64": err,
+        "smoother_glups_fp64": round(glups64, 1),
+        "smoother_glups_fp32": round(glups32, 1),
+        "smoother_light_speed_glups_fp64_24B": round(light_speed_glups(HBM_PEAK_GBS, 24), 1),
+        "roofline": {
+            "kernel": f"{SMOOTHER_KERNEL}<double, 2 sweeps> (fine level)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bytes_launch,
+            "launch_ms": round(t_launch, 4),
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(f_np, levels, info64.cycles)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,95 @@
+"""ctypes binding of libmg.so (argument marshalling only; every step runs in HIP kernels).
+
+The library is loaded from the package directory.  There is no fallback: if libmg.so is
+missing or cannot be loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmg.so")
+
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_ENOCONV, MG_ENAN, MG_ESTATE = range(7)
+STATUS_NAMES = {0: "MG_OK", 1: "MG_EINVAL", 2: "MG_ENOMEM", 3: "MG_EHIP", 4: "MG_ENOCONV",
+                5: "MG_ENAN", 6: "MG_ESTATE"}
+MG_F64, MG_F32_IR = 0, 1
+
+# every function declared in include/mg.h
+EXPORTS = [
+    "mg_validate", "mg_workspace_bytes", "mg_setup", "mg_set_coefficients", "mg_vcycle",
+    "mg_solve", "mg_solve_adjoint", "mg_grad", "mg_smooth", "mg_smooth_f32", "mg_residual",
+    "mg_restrict_residual", "mg_restrict_residual_f32", "mg_prolong_correct",
+    "mg_prolong_correct_f32", "mg_coarsest_solve", "mg_residual_norm2",
+    "mg_set_fused_smoother", "mg_last_error", "mg_destroy",
+]
+
+
+class MgGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("levels", ctypes.c_int),
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("precision", ctypes.c_int), ("variable", ctypes.c_int)]
+
+
+class MgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmg.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2403_08063_amd.build_lib`")
+    L = ctypes.CDLL(LIB_PATH)
+    i, d, P, S = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    G = ctypes.POINTER(MgGrid)
+    PI, PD = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "mg_validate": (i, [G]),
+        "mg_workspace_bytes": (S, [G]),
+        "mg_setup": (i, [G, P, S, P, ctypes.POINTER(P)]),
+        "mg_set_coefficients": (i, [P, P]),
+        "mg_vcycle": (i, [P, P, P]),
+        "mg_solve": (i, [P, P, P, d, PI, PD]),
+        "mg_solve_adjoint": (i, [P, P, P, d, PI, PD]),
+        "mg_grad": (i, [P, P, P, P, P]),
+        "mg_smooth": (i, [P, i, P, P, i]),
+        "mg_smooth_f32": (i, [P, i, P, P, i]),
+        "mg_residual": (i, [P, i, P, P, P]),
+        "mg_restrict_residual": (i, [P, i, P, P, P]),
+        "mg_restrict_residual_f32": (i, [P, i, P, P, P]),
+        "mg_prolong_correct": (i, [P, i, P, P]),
+        "mg_prolong_correct_f32": (i, [P, i, P, P]),
+        "mg_coarsest_solve": (i, [P, P, P]),
+        "mg_residual_norm2": (i, [P, P, P, PD]),
+        "mg_set_fused_smoother": (i, [P, i]),
+        "mg_last_error": (ctypes.c_char_p, [P]),
+        "mg_destroy": (None, [P]),
+    }
+    for name in EXPORTS:
+        res, args = sig[name]
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error(ctx=None) -> str:
+    msg = lib().mg_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def check(status: int, ctx=None, allow=()) -> int:
+    if status != MG_OK and status not in allow:
+        raise MgError(status, last_error(ctx))
+    return status

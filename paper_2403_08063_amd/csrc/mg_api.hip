@@ -1,0 +1,558 @@
+// C-ABI of libmg.so: argument validation, workspace layout, and the host drivers of the
+// V-cycle, the FP32-inner / FP64-outer iterative refinement, the adjoint solve and the
+// gradient pass.  All arithmetic runs in the kernels of mg_kernels.hip and
+// mg_smooth_tiled.hip; the host only sequences launches and reads one norm per cycle.
+//
+// Paper: Angersbach, Kuckuk, Koestler, "Towards Code Generation for Octree-Based Multigrid
+// Solvers": V-cycle Sect. 1 and 5, residual-norm termination Sect. 5, per-level scalars
+// (level size, mesh width) passed to the kernels as arguments as in Sect. 4.3.
+#include "../../include/mg.h"
+#include "mg_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarse = 1024;  // interior unknowns of the coarsest level
+constexpr size_t kAlign = 256;
+
+thread_local char g_err[512] = "no error";
+
+struct Level {
+  int n = 0;
+  size_t N = 0;  // nodes
+  double h = 0;
+  double *u = nullptr, *f = nullptr, *t = nullptr, *k = nullptr;
+  float *u32 = nullptr, *f32 = nullptr, *t32 = nullptr, *k32 = nullptr;
+};
+
+}  // namespace
+
+struct mg_ctx {
+  mg_grid g{};
+  hipStream_t s = nullptr;
+  Level lv[kMaxLevels];
+  int m = 0;  // coarsest interior unknowns
+  double* chol = nullptr;
+  double* ainv = nullptr;
+  int* flag = nullptr;
+  double* partial = nullptr;
+  double* scal = nullptr;  // device scalars: [0] norm2, [1] rhs norm2
+  bool coeffs = false;
+  bool fused = true;
+  char err[512] = "no error";
+};
+
+namespace {
+
+mg_status fail(mg_ctx* c, mg_status st, const char* fmt, ...)
+{
+  char* buf = c ? c->err : g_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 512, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+size_t nodes(int dim, int n) { return dim == 3 ? (size_t)n * n * n : (size_t)n * n; }
+
+mg_status validate(const mg_grid* g, mg_ctx* c)
+{
+  if (!g) return fail(c, MG_EINVAL, "grid description is NULL");
+  if (g->dim != 2 && g->dim != 3) return fail(c, MG_EINVAL, "dim must be 2 or 3 (got %d)", g->dim);
+  if (g->levels < 2 || g->levels > kMaxLevels)
+    return fail(c, MG_EINVAL, "levels must be in [2, %d] (got %d)", kMaxLevels, g->levels);
+  if (g->n < 5) return fail(c, MG_EINVAL, "n must be >= 5 (got %d)", g->n);
+  if ((g->dim == 3 && g->n > 4097) || (g->dim == 2 && g->n > 65537))
+    return fail(c, MG_EINVAL, "n = %d too large", g->n);
+  const int step = 1 << (g->levels - 1);
+  if ((g->n - 1) % step != 0)
+    return fail(c, MG_EINVAL, "n - 1 = %d is not divisible by 2^(levels-1) = %d", g->n - 1, step);
+  const int nc = (g->n - 1) / step + 1;
+  if (nc < 3) return fail(c, MG_EINVAL, "coarsest level has %d nodes per side (< 3)", nc);
+  const long long m = g->dim == 3 ? (long long)(nc - 2) * (nc - 2) * (nc - 2)
+                                  : (long long)(nc - 2) * (nc - 2);
+  if (m > kMaxCoarse)
+    return fail(c, MG_EINVAL, "coarsest level has %lld interior nodes (> %d): use more levels",
+                m, kMaxCoarse);
+  if (g->nu1 < 0 || g->nu2 < 0 || g->nu1 + g->nu2 < 1)
+    return fail(c, MG_EINVAL, "nu1, nu2 must be >= 0 with nu1 + nu2 >= 1");
+  if (g->max_cycles < 1) return fail(c, MG_EINVAL, "max_cycles must be >= 1");
+  if (g->precision != MG_F64 && g->precision != MG_F32_IR)
+    return fail(c, MG_EINVAL, "precision must be MG_F64 or MG_F32_IR");
+  if (g->variable != 0 && g->variable != 1) return fail(c, MG_EINVAL, "variable must be 0 or 1");
+  return MG_OK;
+}
+
+// Workspace layout, shared by mg_workspace_bytes (p == nullptr: count only) and mg_setup.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count)
+  {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+void layout(const mg_grid* g, Carver& cv, mg_ctx* c)
+{
+  Level tmp[kMaxLevels];
+  Level* lv = c ? c->lv : tmp;
+  const bool ir = g->precision == MG_F32_IR;
+  for (int l = 0; l < g->levels; ++l) {
+    Level& L = lv[l];
+    L.n = (g->n - 1) / (1 << l) + 1;
+    L.N = nodes(g->dim, L.n);
+    L.h = (double)(1 << l) / (double)(g->n - 1);
+    L.t = cv.take<double>(L.N);
+    if (l > 0) {
+      L.u = cv.take<double>(L.N);
+      L.f = cv.take<double>(L.N);
+    }
+    if (g->variable) L.k = cv.take<double>(L.N);
+    if (ir) {
+      L.u32 = cv.take<float>(L.N);
+      L.f32 = cv.take<float>(L.N);
+      L.t32 = cv.take<float>(L.N);
+      if (g->variable) L.k32 = cv.take<float>(L.N);
+    }
+  }
+  const int nc = lv[g->levels - 1].n;
+  const int m = g->dim == 3 ? (nc - 2) * (nc - 2) * (nc - 2) : (nc - 2) * (nc - 2);
+  double* chol = cv.take<double>((size_t)m * m);
+  double* ainv = cv.take<double>((size_t)m * m);
+  double* partial = cv.take<double>(mgk::kNormBlocks);
+  double* scal = cv.take<double>(8);
+  int* flag = cv.take<int>(4);
+  if (c) {
+    c->m = m;
+    c->chol = chol;
+    c->ainv = ainv;
+    c->partial = partial;
+    c->scal = scal;
+    c->flag = flag;
+  }
+}
+
+mg_status hip_check(mg_ctx* c, hipError_t e, const char* what)
+{
+  if (e == hipSuccess) return MG_OK;
+  return fail(c, MG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+mg_status launch_check(mg_ctx* c, const char* what)
+{
+  return hip_check(c, hipGetLastError(), what);
+}
+
+// ---------------------------------------------------------------- level views
+template <typename T>
+struct View {
+  T *u, *f, *t;
+  const T* k;
+};
+
+template <typename T>
+View<T> view(mg_ctx* c, int l);
+template <>
+View<double> view<double>(mg_ctx* c, int l)
+{
+  Level& L = c->lv[l];
+  return {L.u, L.f, L.t, L.k};
+}
+template <>
+View<float> view<float>(mg_ctx* c, int l)
+{
+  Level& L = c->lv[l];
+  return {L.u32, L.f32, L.t32, L.k32};
+}
+
+bool use_tiled(const mg_ctx* c, int l)
+{
+  return c->fused && mgk::rbgs_tiled_supported(c->g.dim, c->lv[l].n);
+}
+
+// `sweeps` red-black sweeps on level l.  u holds the iterate, t is the level's second
+// buffer (same boundary values as u).  Returns the buffer that holds the result: the
+// fused kernel works out of place and alternates between u and t.  zero_guess: u is known
+// to be 0 (a coarse-grid correction) and is not read.
+template <typename T>
+T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool zero_guess)
+{
+  const Level& L = c->lv[l];
+  const int dim = c->g.dim;
+  if (sweeps == 0) {
+    if (zero_guess) mgk::fill<T>(c->s, L.N, T(0), u);
+    return u;
+  }
+  if (use_tiled(c, l)) {
+    T* cur = u;
+    T* other = t;
+    int left = sweeps;
+    bool zero = zero_guess;
+    const int maxsw = mgk::rbgs_tiled_max_sweeps(k != nullptr, sizeof(T));
+    while (left > 0) {
+      const int sw = left >= maxsw ? maxsw : left;
+      mgk::rbgs_tiled<T>(c->s, L.n, L.h, k, f, cur, other, sw, zero);
+      T* x = cur;
+      cur = other;
+      other = x;
+      left -= sw;
+      zero = false;
+    }
+    return cur;
+  }
+  if (zero_guess) mgk::fill<T>(c->s, L.N, T(0), u);
+  for (int s = 0; s < sweeps; ++s) {
+    mgk::rbgs_colour<T>(c->s, dim, L.n, L.h, k, f, u, 0);
+    mgk::rbgs_colour<T>(c->s, dim, L.n, L.h, k, f, u, 1);
+  }
+  return u;
+}
+
+// One V(nu1,nu2)-cycle on level l for A_l x = f with x in u (or, when zero_guess, x = 0).
+// Returns the buffer (u or t) holding the new iterate.
+template <typename T>
+T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
+{
+  const int dim = c->g.dim;
+  const Level& L = c->lv[l];
+  const View<T> V = view<T>(c, l);
+  if (l == c->g.levels - 1) {
+    mgk::coarsest_solve<T>(c->s, dim, L.n, c->ainv, f, u);
+    return u;
+  }
+  T* cur = smooth<T>(c, l, u, t, f, V.k, c->g.nu1, zero_guess);
+  const View<T> C = view<T>(c, l + 1);
+  mgk::restrict_residual<T>(c->s, dim, L.n, L.h, V.k, f, cur, C.f);
+  T* ec = cycle<T>(c, l + 1, C.u, C.t, C.f, true);
+  mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, cur);
+  T* other = cur == u ? t : u;
+  return smooth<T>(c, l, cur, other, f, V.k, c->g.nu2, false);
+}
+
+mg_status read_scalar(mg_ctx* c, const double* dev, double* host)
+{
+  mg_status st = hip_check(c, hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, c->s),
+                           "reading a norm");
+  if (st) return st;
+  return hip_check(c, hipStreamSynchronize(c->s), "stream synchronisation");
+}
+
+// Power of two nearest (in log2) to the root-mean-square of a residual of norm rn.  The
+// FP32 right-hand side is r / scale; a power of two changes no float result and keeps the
+// values far from the float range limits.
+double ir_scale(const mg_ctx* c, double rn)
+{
+  const int n = c->g.n;
+  const double m = c->g.dim == 3 ? (double)(n - 2) * (n - 2) * (n - 2) : (double)(n - 2) * (n - 2);
+  const double rms = rn / std::sqrt(m);
+  if (!(rms > 0) || !std::isfinite(rms)) return 1.0;
+  return std::ldexp(1.0, (int)std::lround(std::log2(rms)));
+}
+
+// One outer step of iterative refinement (FP64 u, f): r32 = (f - A u)/scale, e32 = one
+// FP32 V-cycle from e = 0, u += scale * e32.
+mg_status ir_step(mg_ctx* c, const double* f, double* u, double scale)
+{
+  const int dim = c->g.dim;
+  Level& L0 = c->lv[0];
+  mgk::ir_residual(c->s, dim, L0.n, L0.h, L0.k, f, u, 1.0 / scale, L0.f32, c->partial,
+                   c->scal);
+  float* e = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+  mgk::ir_update(c->s, dim, L0.n, scale, e, u);
+  return launch_check(c, "refinement step");
+}
+
+// One FP64 cycle on the caller's (f, u); the result ends in u.
+mg_status f64_cycle(mg_ctx* c, const double* f, double* u)
+{
+  Level& L0 = c->lv[0];
+  double* r = cycle<double>(c, 0, u, L0.t, f, false);
+  if (r != u) mgk::copy<double>(c->s, L0.N, r, u);
+  return launch_check(c, "V-cycle");
+}
+
+mg_status check_ready(mg_ctx* c)
+{
+  if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
+  if (c->g.variable && !c->coeffs)
+    return fail(c, MG_ESTATE, "variable-coefficient context: call mg_set_coefficients first");
+  return MG_OK;
+}
+
+mg_status solve_impl(mg_ctx* c, const double* f, double* u, double tol, int* cycles,
+                     double* relres)
+{
+  if (mg_status st = check_ready(c)) return st;
+  if (!f || !u) return fail(c, MG_EINVAL, "f and u must be non-NULL");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(c, MG_EINVAL, "tol must be > 0");
+  const int dim = c->g.dim;
+  Level& L0 = c->lv[0];
+  if (use_tiled(c, 0)) mgk::copy_boundary(c->s, dim, L0.n, u, L0.t);
+  double bn2 = 0, rn2 = 0;
+  mgk::resid_norm2(c->s, dim, L0.n, L0.h, L0.k, f, u, 1, c->partial, c->scal + 1);
+  mgk::resid_norm2(c->s, dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+  if (mg_status st = launch_check(c, "norm")) return st;
+  if (mg_status st = read_scalar(c, c->scal + 1, &bn2)) return st;
+  if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
+  double bn = std::sqrt(bn2);
+  if (!(bn > 0)) bn = 1.0;
+  double rn = std::sqrt(rn2);
+  double rel = rn / bn;
+  int k = 0;
+  mg_status st = MG_OK;
+  while (std::isfinite(rel) && rel > tol && k < c->g.max_cycles) {
+    if (c->g.precision == MG_F32_IR) st = ir_step(c, f, u, ir_scale(c, rn));
+    else st = f64_cycle(c, f, u);
+    if (st) break;
+    ++k;
+    mgk::resid_norm2(c->s, dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+    if ((st = launch_check(c, "norm"))) break;
+    if ((st = read_scalar(c, c->scal, &rn2))) break;
+    rn = std::sqrt(rn2);
+    rel = rn / bn;
+  }
+  if (cycles) *cycles = k;
+  if (relres) *relres = rel;
+  if (st) return st;
+  if (!std::isfinite(rel)) return fail(c, MG_ENAN, "residual norm is not finite after %d cycles", k);
+  if (rel > tol)
+    return fail(c, MG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", rel, tol, k);
+  return MG_OK;
+}
+
+mg_status level_check(mg_ctx* c, int level, bool needs_coarser)
+{
+  if (mg_status st = check_ready(c)) return st;
+  if (level < 0 || level >= c->g.levels || (needs_coarser && level >= c->g.levels - 1))
+    return fail(c, MG_EINVAL, "level %d out of range", level);
+  return MG_OK;
+}
+
+template <typename T>
+mg_status smooth_impl(mg_ctx* c, int level, const T* f, T* u, int sweeps)
+{
+  if (mg_status st = level_check(c, level, false)) return st;
+  if (!f || !u || sweeps < 0) return fail(c, MG_EINVAL, "bad smoothing arguments");
+  const Level& L = c->lv[level];
+  const View<T> V = view<T>(c, level);
+  if (!V.t) return fail(c, MG_ESTATE, "FP32 arrays exist only in MG_F32_IR contexts");
+  if (c->g.variable && !V.k) return fail(c, MG_ESTATE, "no coefficients for this precision");
+  // the level's second buffer holds the Dirichlet data of u while the fused kernel
+  // alternates between the two
+  T* t = V.t;
+  if (use_tiled(c, level)) {
+    if (sizeof(T) == 8)
+      mgk::copy_boundary(c->s, c->g.dim, L.n, reinterpret_cast<const double*>(u),
+                         reinterpret_cast<double*>(t));
+    else
+      mgk::copy<T>(c->s, L.N, u, t);
+  }
+  T* r = smooth<T>(c, level, u, t, f, V.k, sweeps, false);
+  if (r != u) mgk::copy<T>(c->s, L.N, r, u);
+  return launch_check(c, "smoothing");
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+mg_status mg_validate(const mg_grid* grid) { return validate(grid, nullptr); }
+
+size_t mg_workspace_bytes(const mg_grid* grid)
+{
+  if (validate(grid, nullptr) != MG_OK) return 0;
+  Carver cv{nullptr};
+  layout(grid, cv, nullptr);
+  return cv.off + kAlign;
+}
+
+mg_status mg_setup(const mg_grid* grid, void* workspace, size_t bytes, void* stream, mg_ctx** out)
+{
+  if (!out) return fail(nullptr, MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (mg_status st = validate(grid, nullptr)) return st;
+  if (!workspace) return fail(nullptr, MG_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(nullptr, MG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  const size_t need = mg_workspace_bytes(grid);
+  if (bytes < need)
+    return fail(nullptr, MG_ENOMEM, "workspace of %zu bytes < %zu required", bytes, need);
+  mg_ctx* c = new (std::nothrow) mg_ctx;
+  if (!c) return fail(nullptr, MG_ENOMEM, "host allocation of the context failed");
+  c->g = *grid;
+  c->s = static_cast<hipStream_t>(stream);
+  Carver cv{static_cast<char*>(workspace)};
+  layout(grid, cv, c);
+  // zero the whole workspace once: coarse boundaries (zero Dirichlet data of corrections)
+  // and the boundaries of the second buffers are never written afterwards
+  mgk::fill<double>(c->s, need / sizeof(double), 0.0, static_cast<double*>(workspace));
+  if (!grid->variable) {
+    const Level& Lc = c->lv[grid->levels - 1];
+    mgk::coarsest_factor(c->s, grid->dim, Lc.n, Lc.h, nullptr, c->chol, c->ainv, c->flag);
+  }
+  if (mg_status st = launch_check(c, "setup")) {
+    snprintf(g_err, sizeof g_err, "%s", c->err);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return MG_OK;
+}
+
+mg_status mg_set_coefficients(mg_ctx* c, const double* k)
+{
+  if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
+  if (!c->g.variable) return fail(c, MG_ESTATE, "constant-coefficient context");
+  if (!k) return fail(c, MG_EINVAL, "k is NULL");
+  const int dim = c->g.dim;
+  mgk::copy<double>(c->s, c->lv[0].N, k, c->lv[0].k);
+  for (int l = 1; l < c->g.levels; ++l) mgk::coarsen_k(c->s, dim, c->lv[l - 1].n, c->lv[l - 1].k, c->lv[l].k);
+  if (c->g.precision == MG_F32_IR)
+    for (int l = 0; l < c->g.levels; ++l) mgk::cast_to_f32(c->s, c->lv[l].N, c->lv[l].k, c->lv[l].k32);
+  const Level& Lc = c->lv[c->g.levels - 1];
+  mgk::coarsest_factor(c->s, dim, Lc.n, Lc.h, Lc.k, c->chol, c->ainv, c->flag);
+  if (mg_status st = launch_check(c, "set_coefficients")) return st;
+  c->coeffs = true;
+  return MG_OK;
+}
+
+mg_status mg_vcycle(mg_ctx* c, const double* f, double* u)
+{
+  if (mg_status st = check_ready(c)) return st;
+  if (!f || !u) return fail(c, MG_EINVAL, "f and u must be non-NULL");
+  Level& L0 = c->lv[0];
+  if (use_tiled(c, 0)) mgk::copy_boundary(c->s, c->g.dim, L0.n, u, L0.t);
+  if (c->g.precision == MG_F32_IR) {
+    double rn2 = 0;
+    mgk::resid_norm2(c->s, c->g.dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+    if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
+    return ir_step(c, f, u, ir_scale(c, std::sqrt(rn2)));
+  }
+  return f64_cycle(c, f, u);
+}
+
+mg_status mg_solve(mg_ctx* c, const double* f, double* u, double tol, int* cycles,
+                   double* relres)
+{
+  return solve_impl(c, f, u, tol, cycles, relres);
+}
+
+mg_status mg_solve_adjoint(mg_ctx* c, const double* g, double* lambda, double tol, int* cycles,
+                           double* relres)
+{
+  if (mg_status st = check_ready(c)) return st;
+  if (!g || !lambda) return fail(c, MG_EINVAL, "g and lambda must be non-NULL");
+  mgk::zero_boundary(c->s, c->g.dim, c->g.n, lambda);
+  return solve_impl(c, g, lambda, tol, cycles, relres);
+}
+
+mg_status mg_grad(mg_ctx* c, const double* u, const double* lambda, double* dk, double* df)
+{
+  if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
+  if (!u || !lambda) return fail(c, MG_EINVAL, "u and lambda must be non-NULL");
+  mgk::grad(c->s, c->g.dim, c->g.n, u, lambda, dk, df);
+  return launch_check(c, "gradient");
+}
+
+mg_status mg_smooth(mg_ctx* c, int level, const double* f, double* u, int sweeps)
+{
+  return smooth_impl<double>(c, level, f, u, sweeps);
+}
+
+mg_status mg_smooth_f32(mg_ctx* c, int level, const float* f, float* u, int sweeps)
+{
+  return smooth_impl<float>(c, level, f, u, sweeps);
+}
+
+mg_status mg_residual(mg_ctx* c, int level, const double* f, const double* u, double* r)
+{
+  if (mg_status st = level_check(c, level, false)) return st;
+  if (!f || !u || !r) return fail(c, MG_EINVAL, "NULL array");
+  const Level& L = c->lv[level];
+  mgk::residual<double>(c->s, c->g.dim, L.n, L.h, L.k, f, u, r);
+  return launch_check(c, "residual");
+}
+
+mg_status mg_restrict_residual(mg_ctx* c, int level, const double* f, const double* u, double* fc)
+{
+  if (mg_status st = level_check(c, level, true)) return st;
+  if (!f || !u || !fc) return fail(c, MG_EINVAL, "NULL array");
+  const Level& L = c->lv[level];
+  mgk::zero_boundary(c->s, c->g.dim, c->lv[level + 1].n, fc);
+  mgk::restrict_residual<double>(c->s, c->g.dim, L.n, L.h, L.k, f, u, fc);
+  return launch_check(c, "restriction");
+}
+
+mg_status mg_restrict_residual_f32(mg_ctx* c, int level, const float* f, const float* u, float* fc)
+{
+  if (mg_status st = level_check(c, level, true)) return st;
+  if (!f || !u || !fc) return fail(c, MG_EINVAL, "NULL array");
+  if (c->g.precision != MG_F32_IR) return fail(c, MG_ESTATE, "FP32 path needs an MG_F32_IR context");
+  const Level& L = c->lv[level];
+  mgk::fill<float>(c->s, c->lv[level + 1].N, 0.0f, fc);
+  mgk::restrict_residual<float>(c->s, c->g.dim, L.n, L.h, L.k32, f, u, fc);
+  return launch_check(c, "restriction");
+}
+
+mg_status mg_prolong_correct(mg_ctx* c, int level, const double* ec, double* u)
+{
+  if (mg_status st = level_check(c, level, true)) return st;
+  if (!ec || !u) return fail(c, MG_EINVAL, "NULL array");
+  mgk::prolong_add<double>(c->s, c->g.dim, c->lv[level + 1].n, ec, u);
+  return launch_check(c, "prolongation");
+}
+
+mg_status mg_prolong_correct_f32(mg_ctx* c, int level, const float* ec, float* u)
+{
+  if (mg_status st = level_check(c, level, true)) return st;
+  if (!ec || !u) return fail(c, MG_EINVAL, "NULL array");
+  mgk::prolong_add<float>(c->s, c->g.dim, c->lv[level + 1].n, ec, u);
+  return launch_check(c, "prolongation");
+}
+
+mg_status mg_coarsest_solve(mg_ctx* c, const double* f, double* u)
+{
+  if (mg_status st = check_ready(c)) return st;
+  if (!f || !u) return fail(c, MG_EINVAL, "NULL array");
+  const Level& L = c->lv[c->g.levels - 1];
+  mgk::coarsest_solve<double>(c->s, c->g.dim, L.n, c->ainv, f, u);
+  return launch_check(c, "coarsest solve");
+}
+
+mg_status mg_residual_norm2(mg_ctx* c, const double* f, const double* u, double* norm2)
+{
+  if (mg_status st = check_ready(c)) return st;
+  if (!f || !u || !norm2) return fail(c, MG_EINVAL, "NULL argument");
+  const Level& L0 = c->lv[0];
+  mgk::resid_norm2(c->s, c->g.dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+  if (mg_status st = launch_check(c, "norm")) return st;
+  return read_scalar(c, c->scal, norm2);
+}
+
+mg_status mg_set_fused_smoother(mg_ctx* c, int fused)
+{
+  if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
+  c->fused = fused != 0;
+  return MG_OK;
+}
+
+const char* mg_last_error(const mg_ctx* c) { return c ? c->err : g_err; }
+
+void mg_destroy(mg_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal launch interface between the C-ABI host code (mg_api.hip) and the HIP kernels.
+// Every launcher enqueues on the given stream and returns without synchronising.
+// Arrays are device pointers to n^dim node values in C order [z][y][x], boundary included;
+// k == nullptr selects the constant-coefficient operator.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace mgk {
+
+constexpr int kNormBlocks = 1024;  // fixed grid of the norm kernels: the reduction order
+                                   // depends on nothing but the grid size
+
+// One red-black half-sweep of one colour, in place (every level, 2D and 3D).
+template <typename T>
+void rbgs_colour(hipStream_t s, int dim, int n, double h, const T* k, const T* f, T* u,
+                 int colour);
+
+// `sweeps` (1 or 2) full red-black sweeps fused in one pass over a 3D level, out of place:
+// uout = RBGS^sweeps(uin).  zero_in: treat uin as identically 0 (not read).  The boundary
+// of uout is not written.
+template <typename T>
+void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin,
+                T* uout, int sweeps, bool zero_in);
+// Whether the fused pass serves this level (3D, large enough for its tiles), and how many
+// sweeps one pass may fuse.
+bool rbgs_tiled_supported(int dim, int n);
+int rbgs_tiled_max_sweeps(bool var, size_t value_bytes);
+
+// r = f - A u (interior), 0 on the boundary.
+template <typename T>
+void residual(hipStream_t s, int dim, int n, double h, const T* k, const T* f, const T* u,
+              T* r);
+
+// fc = FW(f - A u) on coarse interior nodes (coarse boundary not written).
+template <typename T>
+void restrict_residual(hipStream_t s, int dim, int nf, double h, const T* k, const T* f,
+                       const T* u, T* fc);
+
+// u += P ec on fine interior nodes (nc = coarse nodes per side).
+template <typename T>
+void prolong_add(hipStream_t s, int dim, int nc, const T* ec, T* u);
+
+// Coarsest level: assemble the interior operator, Cholesky-factor it and form its inverse
+// (one workgroup).  work: m*m doubles; ainv: m*m doubles; flag: set to 1 if the matrix is
+// not positive definite.
+void coarsest_factor(hipStream_t s, int dim, int n, double h, const double* k, double* work,
+                     double* ainv, int* flag);
+// Interior of u = ainv * (interior of f), computed in double; boundary untouched.
+template <typename T>
+void coarsest_solve(hipStream_t s, int dim, int n, const double* ainv, const T* f, T* u);
+
+// partial[0..kNormBlocks) = per-block sums of squares of f - A u over interior nodes
+// (mode 0), or of f - A u_B with u_B = u with zero interior (mode 1: the full right-hand
+// side).  Then out[0] = fixed-order sum of the partials.
+void resid_norm2(hipStream_t s, int dim, int n, double h, const double* k, const double* f,
+                 const double* u, int mode, double* partial, double* out);
+
+// Iterative refinement: r32 = (float)((f - A u) * inv_scale) on interior nodes, plus the
+// norm as in resid_norm2 (mode 0) into out[0].
+void ir_residual(hipStream_t s, int dim, int n, double h, const double* k, const double* f,
+                 const double* u, double inv_scale, float* r32, double* partial, double* out);
+// u += scale * (double)e32 on interior nodes.
+void ir_update(hipStream_t s, int dim, int n, double scale, const float* e32, double* u);
+
+// Coefficient hierarchy: kc = coarse coefficient of k (exp of full-weighted log k in the
+// interior, injection on the boundary).
+void coarsen_k(hipStream_t s, int dim, int nf, const double* k, double* kc);
+void cast_to_f32(hipStream_t s, size_t count, const double* src, float* dst);
+
+// Gradient pass: dk (nullable), df (nullable) from u and lambda on all nodes.
+void grad(hipStream_t s, int dim, int n, const double* u, const double* lam, double* dk,
+          double* df);
+
+template <typename T>
+void fill(hipStream_t s, size_t count, T value, T* p);
+template <typename T>
+void copy(hipStream_t s, size_t count, const T* src, T* dst);
+// Copies the boundary nodes of src into dst.
+void copy_boundary(hipStream_t s, int dim, int n, const double* src, double* dst);
+// Sets the boundary nodes of p to 0.
+void zero_boundary(hipStream_t s, int dim, int n, double* p);
+
+}  // namespace mgk

@@ -1,0 +1,95 @@
+"""Host side of the C ABI (no GPU): the library loads, exports every function that
+include/mg.h declares, validates grid descriptions and sizes workspaces without any HIP
+call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2403_08063_amd import _lib
+from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgGrid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def grid(**kw):
+    g = dict(dim=3, n=513, levels=9, nu1=2, nu2=2, max_cycles=100, precision=0, variable=0)
+    g.update(kw)
+    return MgGrid(**g)
+
+
+def validate(g):
+    return _lib.lib().mg_validate(ctypes.byref(g))
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(dim=2, n=129, levels=6), dict(n=257, levels=8),
+                                dict(precision=1, variable=1), dict(n=65, levels=4),
+                                dict(n=97, levels=6)])
+def test_valid_grids(kw):
+    assert validate(grid(**kw)) == MG_OK
+    assert _lib.lib().mg_workspace_bytes(ctypes.byref(grid(**kw))) > 0
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dim=4), "dim"),
+    (dict(n=512), "divisible"),
+    (dict(levels=10), "coarsest level has 2"),
+    (dict(levels=11), "divisible"),
+    (dict(levels=1), "levels"),
+    (dict(n=513, levels=3), "interior nodes"),
+    (dict(nu1=0, nu2=0), "nu1"),
+    (dict(nu1=-1), "nu1"),
+    (dict(max_cycles=0), "max_cycles"),
+    (dict(precision=2), "precision"),
+    (dict(variable=2), "variable"),
+    (dict(n=3, levels=2), "n must"),
+])
+def test_invalid_grids(kw, msg):
+    g = grid(**kw)
+    assert validate(g) == MG_EINVAL
+    assert msg in _lib.last_error(None)
+    assert _lib.lib().mg_workspace_bytes(ctypes.byref(g)) == 0
+
+
+def test_null_grid():
+    assert _lib.lib().mg_validate(None) == MG_EINVAL
+
+
+def test_workspace_scales_with_forms():
+    ws = lambda **kw: _lib.lib().mg_workspace_bytes(ctypes.byref(grid(**kw)))
+    base = ws()
+    n3 = 513 ** 3
+    # FP64: one second buffer on the fine level plus u, f, t on the coarse levels
+    assert n3 * 8 <= base <= n3 * 8 * 1.6
+    assert ws(precision=1) > base + 3 * n3 * 4  # FP32 e, r, t on the fine level
+    assert ws(variable=1) > base + n3 * 8       # coefficient hierarchy
+
+
+def test_setup_rejects_bad_arguments_before_gpu_work():
+    lib = _lib.lib()
+    out = ctypes.c_void_p(1)
+    g = grid(n=65, levels=4)
+    assert lib.mg_setup(ctypes.byref(g), None, 0, None, ctypes.byref(out)) == MG_EINVAL
+    assert out.value is None
+    assert lib.mg_setup(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == 2
+    assert "workspace" in _lib.last_error(None)
+    assert lib.mg_setup(ctypes.byref(g), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(out)) == MG_EINVAL
+    assert "aligned" in _lib.last_error(None)
+    assert lib.mg_solve(None, None, None, 1e-10, None, None) == MG_EINVAL
