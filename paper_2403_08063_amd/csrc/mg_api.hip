@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 
 namespace {
 
@@ -133,7 +134,7 @@ void layout(const mg_grid* g, Carver& cv, mg_ctx* c)
   const int m = g->dim == 3 ? (nc - 2) * (nc - 2) * (nc - 2) : (nc - 2) * (nc - 2);
   double* chol = cv.take<double>((size_t)m * m);
   double* ainv = cv.take<double>((size_t)m * m);
-  double* partial = cv.take<double>(mgk::kNormBlocks);
+  double* partial = cv.take<double>(mgk::kStreamPartials);
   double* scal = cv.take<double>(8);
   int* flag = cv.take<int>(4);
   if (c) {
@@ -236,7 +237,8 @@ T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
   }
   T* cur = smooth<T>(c, l, u, t, f, V.k, c->g.nu1, zero_guess);
   const View<T> C = view<T>(c, l + 1);
-  mgk::restrict_residual<T>(c->s, dim, L.n, L.h, V.k, f, cur, C.f);
+  if (use_tiled(c, l)) mgk::restrict_residual_tiled<T>(c->s, L.n, L.h, V.k, f, cur, C.f);
+  else mgk::restrict_residual<T>(c->s, dim, L.n, L.h, V.k, f, cur, C.f);
   T* ec = cycle<T>(c, l + 1, C.u, C.t, C.f, true);
   mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, cur);
   T* other = cur == u ? t : u;
@@ -263,8 +265,18 @@ double ir_scale(const mg_ctx* c, double rn)
   return std::ldexp(1.0, (int)std::lround(std::log2(rms)));
 }
 
-// One outer step of iterative refinement (FP64 u, f): r32 = (f - A u)/scale, e32 = one
-// FP32 V-cycle from e = 0, u += scale * e32.
+// ||f - A u||^2 (mode 0) or of the full right-hand side (mode 1) into c->scal[slot].
+void norm2(mg_ctx* c, const double* f, const double* u, int mode, int slot)
+{
+  const Level& L0 = c->lv[0];
+  if (use_tiled(c, 0))
+    mgk::resid_norm2_tiled(c->s, L0.n, L0.h, L0.k, f, u, mode, c->partial, c->scal + slot);
+  else
+    mgk::resid_norm2(c->s, c->g.dim, L0.n, L0.h, L0.k, f, u, mode, c->partial, c->scal + slot);
+}
+
+// One outer step of iterative refinement (FP64 u, f) with the per-step kernels:
+// r32 = (f - A u)/scale, e32 = one FP32 V-cycle from e = 0, u += scale * e32.
 mg_status ir_step(mg_ctx* c, const double* f, double* u, double scale)
 {
   const int dim = c->g.dim;
@@ -293,23 +305,74 @@ mg_status check_ready(mg_ctx* c)
   return MG_OK;
 }
 
+mg_status finish(mg_ctx* c, int k, double rel, double tol, int* cycles, double* relres,
+                 mg_status st)
+{
+  if (cycles) *cycles = k;
+  if (relres) *relres = rel;
+  if (st) return st;
+  if (!std::isfinite(rel)) return fail(c, MG_ENAN, "residual norm is not finite after %d cycles", k);
+  if (rel > tol)
+    return fail(c, MG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", rel, tol, k);
+  return MG_OK;
+}
+
+// Refinement on a large 3D grid with the fused pass (mg_resid_tiled.hip): every pass
+// applies the previous FP32 correction, forms the FP64 residual, its norm and the scaled
+// FP32 right-hand side of the next cycle, writing the updated iterate out of place (u and
+// the level's second buffer alternate).  The scale of a pass's r32 is a power of two taken
+// from the previous residual norm; powers of two change no float result.
+mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, double bn,
+                            int* cycles, double* relres)
+{
+  Level& L0 = c->lv[0];
+  double* cur = u;
+  double* other = L0.t;
+  double scale = ir_scale(c, bn);  // scale of the r32 being written
+  double rn2 = 0;
+  mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other, L0.f32,
+                     c->partial, c->scal);
+  std::swap(cur, other);
+  mg_status st = launch_check(c, "refinement pass");
+  if (!st) st = read_scalar(c, c->scal, &rn2);
+  double rel = std::sqrt(rn2) / bn;
+  int k = 0;
+  while (!st && std::isfinite(rel) && rel > tol && k < c->g.max_cycles) {
+    float* e = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+    const double next = ir_scale(c, std::sqrt(rn2));
+    mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, e, scale, 1.0 / next, other, L0.f32,
+                       c->partial, c->scal);
+    std::swap(cur, other);
+    scale = next;
+    ++k;
+    if ((st = launch_check(c, "refinement pass"))) break;
+    if ((st = read_scalar(c, c->scal, &rn2))) break;
+    rel = std::sqrt(rn2) / bn;
+  }
+  if (cur != u) mgk::copy<double>(c->s, L0.N, cur, u);
+  if (!st) st = launch_check(c, "copy");
+  return finish(c, k, rel, tol, cycles, relres, st);
+}
+
 mg_status solve_impl(mg_ctx* c, const double* f, double* u, double tol, int* cycles,
                      double* relres)
 {
   if (mg_status st = check_ready(c)) return st;
   if (!f || !u) return fail(c, MG_EINVAL, "f and u must be non-NULL");
   if (!(tol > 0) || !std::isfinite(tol)) return fail(c, MG_EINVAL, "tol must be > 0");
-  const int dim = c->g.dim;
   Level& L0 = c->lv[0];
-  if (use_tiled(c, 0)) mgk::copy_boundary(c->s, dim, L0.n, u, L0.t);
+  if (use_tiled(c, 0)) mgk::copy_boundary(c->s, c->g.dim, L0.n, u, L0.t);
   double bn2 = 0, rn2 = 0;
-  mgk::resid_norm2(c->s, dim, L0.n, L0.h, L0.k, f, u, 1, c->partial, c->scal + 1);
-  mgk::resid_norm2(c->s, dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+  norm2(c, f, u, 1, 1);
   if (mg_status st = launch_check(c, "norm")) return st;
   if (mg_status st = read_scalar(c, c->scal + 1, &bn2)) return st;
-  if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
   double bn = std::sqrt(bn2);
   if (!(bn > 0)) bn = 1.0;
+  if (c->g.precision == MG_F32_IR && use_tiled(c, 0))
+    return solve_ir_streamed(c, f, u, tol, bn, cycles, relres);
+  norm2(c, f, u, 0, 0);
+  if (mg_status st = launch_check(c, "norm")) return st;
+  if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
   double rn = std::sqrt(rn2);
   double rel = rn / bn;
   int k = 0;
@@ -319,19 +382,13 @@ mg_status solve_impl(mg_ctx* c, const double* f, double* u, double tol, int* cyc
     else st = f64_cycle(c, f, u);
     if (st) break;
     ++k;
-    mgk::resid_norm2(c->s, dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+    norm2(c, f, u, 0, 0);
     if ((st = launch_check(c, "norm"))) break;
     if ((st = read_scalar(c, c->scal, &rn2))) break;
     rn = std::sqrt(rn2);
     rel = rn / bn;
   }
-  if (cycles) *cycles = k;
-  if (relres) *relres = rel;
-  if (st) return st;
-  if (!std::isfinite(rel)) return fail(c, MG_ENAN, "residual norm is not finite after %d cycles", k);
-  if (rel > tol)
-    return fail(c, MG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", rel, tol, k);
-  return MG_OK;
+  return finish(c, k, rel, tol, cycles, relres, st);
 }
 
 mg_status level_check(mg_ctx* c, int level, bool needs_coarser)
@@ -439,7 +496,7 @@ mg_status mg_vcycle(mg_ctx* c, const double* f, double* u)
   if (use_tiled(c, 0)) mgk::copy_boundary(c->s, c->g.dim, L0.n, u, L0.t);
   if (c->g.precision == MG_F32_IR) {
     double rn2 = 0;
-    mgk::resid_norm2(c->s, c->g.dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+    norm2(c, f, u, 0, 0);
     if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
     return ir_step(c, f, u, ir_scale(c, std::sqrt(rn2)));
   }
@@ -494,7 +551,8 @@ mg_status mg_restrict_residual(mg_ctx* c, int level, const double* f, const doub
   if (!f || !u || !fc) return fail(c, MG_EINVAL, "NULL array");
   const Level& L = c->lv[level];
   mgk::zero_boundary(c->s, c->g.dim, c->lv[level + 1].n, fc);
-  mgk::restrict_residual<double>(c->s, c->g.dim, L.n, L.h, L.k, f, u, fc);
+  if (use_tiled(c, level)) mgk::restrict_residual_tiled<double>(c->s, L.n, L.h, L.k, f, u, fc);
+  else mgk::restrict_residual<double>(c->s, c->g.dim, L.n, L.h, L.k, f, u, fc);
   return launch_check(c, "restriction");
 }
 
@@ -505,7 +563,8 @@ mg_status mg_restrict_residual_f32(mg_ctx* c, int level, const float* f, const f
   if (c->g.precision != MG_F32_IR) return fail(c, MG_ESTATE, "FP32 path needs an MG_F32_IR context");
   const Level& L = c->lv[level];
   mgk::fill<float>(c->s, c->lv[level + 1].N, 0.0f, fc);
-  mgk::restrict_residual<float>(c->s, c->g.dim, L.n, L.h, L.k32, f, u, fc);
+  if (use_tiled(c, level)) mgk::restrict_residual_tiled<float>(c->s, L.n, L.h, L.k32, f, u, fc);
+  else mgk::restrict_residual<float>(c->s, c->g.dim, L.n, L.h, L.k32, f, u, fc);
   return launch_check(c, "restriction");
 }
 
@@ -534,14 +593,13 @@ mg_status mg_coarsest_solve(mg_ctx* c, const double* f, double* u)
   return launch_check(c, "coarsest solve");
 }
 
-mg_status mg_residual_norm2(mg_ctx* c, const double* f, const double* u, double* norm2)
+mg_status mg_residual_norm2(mg_ctx* c, const double* f, const double* u, double* out)
 {
   if (mg_status st = check_ready(c)) return st;
-  if (!f || !u || !norm2) return fail(c, MG_EINVAL, "NULL argument");
-  const Level& L0 = c->lv[0];
-  mgk::resid_norm2(c->s, c->g.dim, L0.n, L0.h, L0.k, f, u, 0, c->partial, c->scal);
+  if (!f || !u || !out) return fail(c, MG_EINVAL, "NULL argument");
+  norm2(c, f, u, 0, 0);
   if (mg_status st = launch_check(c, "norm")) return st;
-  return read_scalar(c, c->scal, norm2);
+  return read_scalar(c, c->scal, out);
 }
 
 mg_status mg_set_fused_smoother(mg_ctx* c, int fused)

@@ -10,6 +10,7 @@ namespace mgk {
 
 constexpr int kNormBlocks = 1024;  // fixed grid of the norm kernels: the reduction order
                                    // depends on nothing but the grid size
+constexpr int kStreamPartials = 16384;  // per-workgroup partial sums of the streaming passes
 
 // One red-black half-sweep of one colour, in place (every level, 2D and 3D).
 template <typename T>
@@ -36,6 +37,20 @@ void residual(hipStream_t s, int dim, int n, double h, const T* k, const T* f, c
 template <typename T>
 void restrict_residual(hipStream_t s, int dim, int nf, double h, const T* k, const T* f,
                        const T* u, T* fc);
+
+// Streaming versions for large 3D levels (mg_resid_tiled.hip): same results up to the
+// summation order.  restrict_residual_tiled writes the coarse interior only.
+template <typename T>
+void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const T* f,
+                             const T* u, T* fc);
+// mode 0: ||f - A u||^2; mode 1: interior of u read as 0.  partial: kStreamPartials doubles.
+void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
+                       const double* u, int mode, double* partial, double* out);
+// Refinement pass: uout = u + scale * e on interior nodes (boundary of uout not written),
+// r = f - A uout, r32 = (float)(r * inv_scale), out[0] = sum of r^2 (interior).
+void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
+                   const double* u, const float* e, double scale, double inv_scale, double* uout,
+                   float* r32, double* partial, double* out);
 
 // u += P ec on fine interior nodes (nc = coarse nodes per side).
 template <typename T>

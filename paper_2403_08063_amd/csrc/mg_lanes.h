@@ -1,0 +1,38 @@
+// Cross-lane moves within one 64-lane wavefront, by DPP (data-parallel primitives) on the
+// VALU instead of an LDS permute: wave_shr:1 gives lane l the value of lane l-1,
+// wave_shl:1 the value of lane l+1; lanes without a source lane receive 0.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mgk {
+
+constexpr int kDppWaveShl1 = 0x130;  // lane l <- lane l+1
+constexpr int kDppWaveShr1 = 0x138;  // lane l <- lane l-1
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+  const int lo = dpp_i32<CTRL>(__double2loint(v));
+  const int hi = dpp_i32<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+
+// value of the lane below (l-1) / above (l+1)
+template <typename T>
+__device__ __forceinline__ T from_lane_below(T v) { return dpp<kDppWaveShr1>(v); }
+template <typename T>
+__device__ __forceinline__ T from_lane_above(T v) { return dpp<kDppWaveShl1>(v); }
+
+}  // namespace mgk

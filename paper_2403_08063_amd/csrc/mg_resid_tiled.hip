@@ -1,0 +1,436 @@
+// Streaming residual kernels for large 3D levels on gfx950: one pass over u and f per call.
+//
+//  - restriction: fc = FW(f - A u) on the coarse interior (full weighting, the tensor
+//    product of (1/4, 1/2, 1/4));
+//  - norm: sum over interior nodes of (f - A u)^2, per-workgroup partial sums reduced
+//    afterwards in a fixed order; optionally with the interior of u read as 0 (the norm
+//    of the full right-hand side);
+//  - refinement pass: u_out = u + s e (e in float), r = f - A u_out, r32 = r * inv_scale
+//    (float), sum of r^2 -- the FP64 update, residual, norm and down-cast of one step of
+//    iterative refinement fused in one pass.
+//
+// Decomposition (as in the fused smoother): a workgroup owns a tile of 128 columns x
+// W*RPW rows of a z-chunk and streams through its planes; lane l of wave w holds columns
+// 2l, 2l+1 of rows w*RPW .. w*RPW+RPW-1.  A lane keeps u on the planes s-1, s, s+1 in
+// registers (the residual's z-neighbours), takes x-neighbours from adjacent lanes by DPP
+// and y-neighbours from its own rows or, across wave boundaries, from edge rows exchanged
+// through LDS one step ahead (double-buffered: one barrier per plane).  Tiles overlap by
+// the one-node halo the residual needs; each output node belongs to exactly one tile.
+//
+// Restriction: lane l's first column is the fine node 2X of coarse column X, so
+// FW_x = r(2X-1)/4 + r(2X)/2 + r(2X+1)/4 needs one DPP; a wave's even rows are fine rows
+// 2Y and FW_y combines rows 2Y-1, 2Y, 2Y+1 one step later (the row above a wave comes from
+// the previous wave through LDS); FW_z accumulates over the fine planes 2Z-1, 2Z, 2Z+1.
+// Paper: the residual-norm stopping test of Sect. 5; the operators of Sect. 5, Eq. 1.
+#include "mg_kernels.h"
+#include "mg_lanes.h"
+#include "mg_stencil.h"
+
+namespace mgk {
+namespace {
+
+enum { kRestrict = 0, kNorm = 1, kRefine = 2 };
+
+template <typename T, bool VAR, int MODE, int W, int RPW>
+struct Stream {
+  static constexpr int BX = 128;
+  static constexpr int BY = W * RPW;
+  // restriction: coarse columns / rows per tile; norm, refinement: fine output per tile
+  static constexpr int CX = 62, CY = BY / 2 - 2;
+  static constexpr int OX = BX - 2, OY = BY - 2;
+  static_assert(RPW % 2 == 0, "fine row parity must be uniform across waves");
+
+  struct Shared {
+    T eu[2][W][2][2][64];  // edge rows of u: [buffer][wave][first/last row][column][lane]
+    T ek[VAR ? 2 : 1][W][2][2][64];
+    T erx[2][W][64];       // restriction: x-filtered residual of a wave's last row
+    double red[W];
+  };
+
+  struct Args {
+    const T* f;
+    const T* u;
+    const T* k;
+    T* out;              // restriction: fc; refinement: u_out
+    const float* e;      // refinement: correction
+    float* r32;          // refinement: scaled residual
+    double* partial;     // norm, refinement
+    double scale;        // refinement: u_out = u + scale * e
+    double inv_scale;    // refinement: r32 = r * inv_scale
+    int zero_interior;   // norm: read the interior of u as 0
+    int n;
+    T ih2;
+    int tiles_x, tiles_y, zlen;
+  };
+
+  __device__ __forceinline__ static void run(const Args& a, Shared& sh)
+  {
+    const int n = a.n;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-aware tile index (workgroup b runs on XCD b % 8)
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int xcd = b & 7, jb = b >> 3, q = nb >> 3, rem = nb & 7;
+    const int t = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + jb;
+    const int tx = t % a.tiles_x, ty = (t / a.tiles_x) % a.tiles_y, tz = t / (a.tiles_x * a.tiles_y);
+
+    int gx0, gy0, sbeg, send;  // fine tile origin, residual planes [sbeg, send]
+    int Z0 = 0, Z1 = 0;
+    if (MODE == kRestrict) {
+      const int nc = (n - 1) / 2 + 1;
+      const int X0 = 1 + tx * CX, Y0 = 1 + ty * CY;
+      Z0 = 1 + tz * a.zlen;
+      Z1 = min(Z0 + a.zlen, nc - 1);
+      gx0 = 2 * X0 - 2;
+      gy0 = 2 * Y0 - 2;
+      sbeg = 2 * Z0 - 1;
+      send = 2 * Z1 - 1;
+    } else {
+      gx0 = tx * OX;  // owned columns: tile columns 1..BX-2
+      gy0 = ty * OY;
+      const int z0 = 1 + tz * a.zlen;
+      sbeg = z0;
+      send = min(z0 + a.zlen, n - 1) - 1;
+    }
+    const int gxa = gx0 + 2 * lane;
+    const int gyw = gy0 + w * RPW;
+
+    int cx[2];
+    bool colin[2], colown[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const int gx = gxa + o, px = 2 * lane + o;
+      cx[o] = min(max(gx, 0), n - 1);
+      colin[o] = gx >= 1 && gx <= n - 2;
+      colown[o] = colin[o] && px >= 1 && px <= BX - 2;
+    }
+    size_t rowoff[RPW];
+    bool rowin[RPW], rowown[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int gy = gyw + i, pr = w * RPW + i;
+      rowoff[i] = (size_t)min(max(gy, 0), n - 1) * (size_t)n;
+      rowin[i] = gy >= 1 && gy <= n - 2;
+      rowown[i] = rowin[i] && pr >= 1 && pr <= BY - 2;
+    }
+    const size_t n2 = (size_t)n * (size_t)n;
+
+    T U[3][RPW][2], F[3][RPW][2], K[3][RPW][2];
+    T PU[RPW][2], PF[RPW][2], PK[RPW][2];
+    auto load = [&](int z) {
+      const size_t zc = (size_t)min(max(z, 0), n - 1);
+      const bool zin = z >= 1 && z <= n - 2;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const size_t r = zc * n2 + rowoff[i];
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          T v = a.u[r + cx[o]];
+          if (MODE == kNorm) {
+            if (a.zero_interior && zin && rowin[i] && colin[o]) v = T(0);
+          }
+          if (MODE == kRefine) {
+            // e == nullptr: no correction to apply (the first pass of a solve)
+            if (a.e != nullptr && zin && rowin[i] && colin[o]) v = v + (T)a.scale * (T)a.e[r + cx[o]];
+          }
+          PU[i][o] = v;
+          PF[i][o] = a.f[r + cx[o]];
+          if (VAR) PK[i][o] = a.k[r + cx[o]];
+        }
+      }
+    };
+    auto shift_in = [&]() {
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          U[0][i][o] = U[1][i][o]; U[1][i][o] = U[2][i][o]; U[2][i][o] = PU[i][o];
+          F[0][i][o] = F[1][i][o]; F[1][i][o] = F[2][i][o]; F[2][i][o] = PF[i][o];
+          if (VAR) { K[0][i][o] = K[1][i][o]; K[1][i][o] = K[2][i][o]; K[2][i][o] = PK[i][o]; }
+        }
+    };
+    auto write_edges = [&](int buf, int slot) {  // first and last row of a queued plane
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        sh.eu[buf][w][0][o][lane] = U[slot][0][o];
+        sh.eu[buf][w][1][o][lane] = U[slot][RPW - 1][o];
+        if (VAR) {
+          sh.ek[buf][w][0][o][lane] = K[slot][0][o];
+          sh.ek[buf][w][1][o][lane] = K[slot][RPW - 1][o];
+        }
+      }
+    };
+
+    // prologue: planes sbeg-1, sbeg, sbeg+1 in the queue, edges of plane sbeg written
+    load(sbeg - 1);
+    shift_in();
+    load(sbeg);
+    shift_in();
+    load(sbeg + 1);
+    shift_in();
+    write_edges(1, 1);  // edges of plane sbeg, read at the first step from buffer 1
+
+    T rxprev[RPW];
+    T acc[RPW / 2];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) rxprev[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < RPW / 2; ++i) acc[i] = T(0);
+    double sumsq = 0.0;
+
+    const int last = MODE == kRestrict ? send + 1 : send;
+    for (int s = sbeg, step = 0; s <= last; ++s, ++step) {
+      const int rb = (step + 1) & 1, wb = step & 1;
+      __syncthreads();
+      if (s + 2 <= send + 1) load(s + 2);
+
+      if (MODE == kRestrict && s > sbeg) {
+        // FW_y of plane s-1 for the coarse rows at even fine rows, then FW_z over the fine
+        // planes 2Z-1 (1/4), 2Z (1/2), 2Z+1 (1/4)
+        const int sp = s - 1;
+        T ry[RPW / 2];
+#pragma unroll
+        for (int i = 0; i < RPW; i += 2) {
+          const T above = i > 0 ? rxprev[i - 1] : (w > 0 ? sh.erx[rb][w - 1][lane] : T(0));
+          ry[i / 2] = (T(0.25) * above + T(0.5) * rxprev[i]) + T(0.25) * rxprev[i + 1];
+        }
+        if (sp & 1) {
+          // plane sp = 2Z+1 completes coarse plane Z and starts plane Z+1
+          const int Z = (sp - 1) / 2;
+          const int nc = (n - 1) / 2 + 1;
+          const bool store = Z >= Z0 && Z < Z1;
+          const size_t zo = (size_t)Z * nc * nc;
+#pragma unroll
+          for (int i = 0; i < RPW; i += 2) {
+            const T done = acc[i / 2] + T(0.25) * ry[i / 2];
+            const int crow = (w * RPW + i) / 2;  // coarse Y = Y0 - 1 + crow
+            const int Y = gy0 / 2 + crow;
+            const int X = gx0 / 2 + lane;
+            if (store && crow >= 1 && crow <= CY && lane >= 1 && lane <= CX && Y <= nc - 2 &&
+                X <= nc - 2)
+              a.out[zo + (size_t)Y * nc + X] = done;
+            acc[i / 2] = T(0.25) * ry[i / 2];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPW; i += 2) acc[i / 2] = acc[i / 2] + T(0.5) * ry[i / 2];
+        }
+      }
+
+      if (s <= send) {
+        // residual at plane s (queue slot 1), every own node
+        T r[RPW][2];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const T l1 = from_lane_below(U[1][i][1]);
+          const T r0 = from_lane_above(U[1][i][0]);
+          T kl1 = T(0), kr0 = T(0);
+          if (VAR) { kl1 = from_lane_below(K[1][i][1]); kr0 = from_lane_above(K[1][i][0]); }
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const T ui = U[1][i][o];
+            const T xm = o == 0 ? l1 : U[1][i][0];
+            const T xp = o == 0 ? U[1][i][1] : r0;
+            T ym = T(0), yp = T(0), kym = T(0), kyp = T(0);
+            if (i > 0) { ym = U[1][i - 1][o]; if (VAR) kym = K[1][i - 1][o]; }
+            else if (w > 0) { ym = sh.eu[rb][w - 1][1][o][lane]; if (VAR) kym = sh.ek[rb][w - 1][1][o][lane]; }
+            if (i < RPW - 1) { yp = U[1][i + 1][o]; if (VAR) kyp = K[1][i + 1][o]; }
+            else if (w < W - 1) { yp = sh.eu[rb][w + 1][0][o][lane]; if (VAR) kyp = sh.ek[rb][w + 1][0][o][lane]; }
+            const T zm = U[0][i][o], zp = U[2][i][o];
+            T au;
+            if (!VAR) {
+              au = au_const<T, 3>(a.ih2, ui, xm, xp, ym, yp, zm, zp);
+            } else {
+              const T kxm = o == 0 ? kl1 : K[1][i][0];
+              const T kxp = o == 0 ? K[1][i][1] : kr0;
+              au = au_var<T, 3>(a.ih2, ui, K[1][i][o], xm, kxm, xp, kxp, ym, kym, yp, kyp, zm,
+                                K[0][i][o], zp, K[2][i][o]);
+            }
+            r[i][o] = F[1][i][o] - au;
+          }
+        }
+        const bool zin = s >= 1 && s <= n - 2;
+        if (MODE == kRestrict) {
+          // fine nodes outside the interior carry no residual
+#pragma unroll
+          for (int i = 0; i < RPW; ++i) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+              r[i][o] = (zin && rowin[i] && colin[o]) ? r[i][o] : T(0);
+            const T left = from_lane_below(r[i][1]);
+            rxprev[i] = (T(0.25) * left + T(0.5) * r[i][0]) + T(0.25) * r[i][1];
+          }
+          sh.erx[wb][w][lane] = rxprev[RPW - 1];
+        } else {
+          const size_t zo = (size_t)s * n2;
+#pragma unroll
+          for (int i = 0; i < RPW; ++i)
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+              if (!(zin && rowown[i] && colown[o])) continue;
+              const double rv = (double)r[i][o];
+              sumsq += rv * rv;
+              if (MODE == kRefine) {
+                const size_t idx = zo + rowoff[i] + cx[o];
+                a.out[idx] = U[1][i][o];
+                a.r32[idx] = (float)(rv * a.inv_scale);
+              }
+            }
+        }
+      }
+      // next step: planes s, s+1, s+2; edges of plane s+1 (slot 2 before the shift)
+      write_edges(wb, 2);
+      shift_in();
+    }
+
+    if (MODE != kRestrict) {
+#pragma unroll
+      for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
+      __syncthreads();
+      if (lane == 0) sh.red[w] = sumsq;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int v = 0; v < W; ++v) tot += sh.red[v];
+        a.partial[blockIdx.x] = tot;
+      }
+    }
+  }
+};
+
+template <typename T, bool VAR, int MODE, int W, int RPW>
+__global__ void __launch_bounds__(64 * W) k_stream(typename Stream<T, VAR, MODE, W, RPW>::Args a)
+{
+  using C = Stream<T, VAR, MODE, W, RPW>;
+  __shared__ typename C::Shared sh;
+  C::run(a, sh);
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_fixed(const double* __restrict__ partial, int count, double* __restrict__ out)
+{
+  __shared__ double part[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+template <typename Kernel>
+int capacity_of(Kernel kernel, int block)
+{
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+      per_cu = 1;
+    cache[dev] = cus * per_cu;
+  }
+  return cache[dev];
+}
+
+// z-chunk length minimising (rounds of resident workgroups) x (planes per workgroup)
+int best_zlen(int per_tile_plane_count, int zext, int halo, int capacity, int max_blocks)
+{
+  long long best = -1;
+  int bestz = zext;
+  for (int c = 1; c <= zext; ++c) {
+    const int zlen = (zext + c - 1) / c;
+    const int chunks = (zext + zlen - 1) / zlen;
+    const long long blocks = (long long)per_tile_plane_count * chunks;
+    if (blocks > max_blocks) break;
+    const long long rounds = (blocks + capacity - 1) / capacity;
+    const long long cost = rounds * (zlen + halo);
+    if (best < 0 || cost < best) { best = cost; bestz = zlen; }
+  }
+  return bestz;
+}
+
+constexpr int kW = 8, kRPW = 4;
+
+}  // namespace
+
+template <typename T>
+void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const T* f,
+                             const T* u, T* fc)
+{
+  const int nc = (nf - 1) / 2 + 1;
+  const int m = nc - 2;
+  auto launch = [&](auto kern, auto argsproto) {
+    using A = decltype(argsproto);
+    A a{};
+    a.f = f; a.u = u; a.k = k; a.out = fc; a.n = nf; a.ih2 = (T)(1.0 / (h * h));
+    a.tiles_x = (m + 61) / 62;
+    a.tiles_y = (m + (kW * kRPW / 2 - 2) - 1) / (kW * kRPW / 2 - 2);
+    const int per = a.tiles_x * a.tiles_y;
+    a.zlen = best_zlen(per, m, 1, capacity_of(kern, 64 * kW), 1 << 30);
+    const int blocks = per * ((m + a.zlen - 1) / a.zlen);
+    kern<<<blocks, 64 * kW, 0, s>>>(a);
+  };
+  if (k) launch(k_stream<T, true, kRestrict, kW, kRPW>, typename Stream<T, true, kRestrict, kW, kRPW>::Args{});
+  else launch(k_stream<T, false, kRestrict, kW, kRPW>, typename Stream<T, false, kRestrict, kW, kRPW>::Args{});
+}
+
+namespace {
+template <bool VAR, int MODE>
+void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, kW, kRPW>::Args a, double* partial,
+                 double* out)
+{
+  using C = Stream<double, VAR, MODE, kW, kRPW>;
+  auto kern = k_stream<double, VAR, MODE, kW, kRPW>;
+  const int m = a.n - 2;
+  a.tiles_x = (m + C::OX - 1) / C::OX;
+  a.tiles_y = (m + C::OY - 1) / C::OY;
+  const int per = a.tiles_x * a.tiles_y;
+  a.zlen = best_zlen(per, m, 2, capacity_of(kern, 64 * kW), kStreamPartials);
+  const int blocks = per * ((m + a.zlen - 1) / a.zlen);
+  a.partial = partial;
+  kern<<<blocks, 64 * kW, 0, s>>>(a);
+  k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
+}
+}  // namespace
+
+void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
+                       const double* u, int mode, double* partial, double* out)
+{
+  if (k) {
+    Stream<double, true, kNorm, kW, kRPW>::Args a{};
+    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
+    launch_fine<true, kNorm>(s, a, partial, out);
+  } else {
+    Stream<double, false, kNorm, kW, kRPW>::Args a{};
+    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
+    launch_fine<false, kNorm>(s, a, partial, out);
+  }
+}
+
+void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
+                   const double* u, const float* e, double scale, double inv_scale, double* uout,
+                   float* r32, double* partial, double* out)
+{
+  if (k) {
+    Stream<double, true, kRefine, kW, kRPW>::Args a{};
+    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
+    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
+    launch_fine<true, kRefine>(s, a, partial, out);
+  } else {
+    Stream<double, false, kRefine, kW, kRPW>::Args a{};
+    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
+    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
+    launch_fine<false, kRefine>(s, a, partial, out);
+  }
+}
+
+template void restrict_residual_tiled<double>(hipStream_t, int, double, const double*,
+                                              const double*, const double*, double*);
+template void restrict_residual_tiled<float>(hipStream_t, int, double, const float*,
+                                             const float*, const float*, float*);
+
+}  // namespace mgk

@@ -29,6 +29,7 @@
 //  - blockIdx -> tile is XCD-aware: a workgroup b runs on XCD b mod 8, so every XCD is given
 //    a contiguous range of tiles, whose shared halo columns and rows then meet in the same L2.
 #include "mg_kernels.h"
+#include "mg_lanes.h"
 #include "mg_stencil.h"
 
 #include <utility>
@@ -65,26 +66,39 @@ struct Tiled {
                                              Shared& sh)
   {
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int gx0 = ox - H;           // global x of tile column 0
-    const int gxa = gx0 + 2 * lane;   // global x of this lane's first column
-    const int gyw = oy - H + w * RPW; // global y of this wave's first row
-    const size_t nn = (size_t)n;
+    // wave index, made explicitly wave-uniform so that row bookkeeping stays scalar
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gxa = ox - H + 2 * lane;  // global x of this lane's first column
+    const int gyw = oy - H + w * RPW;   // global y of this wave's first row
 
-    // validity of this lane's columns and rows (inside the grid) and interior-ness
-    bool colok[2], colin[2], rowok[RPW], rowin[RPW];
+    // Loads use a wave-uniform row pointer plus a per-lane column; coordinates outside the
+    // grid are clamped onto it, so every load is in bounds.  Such positions are never
+    // updated and never read by an updated node (which is interior).
+    int cx[2];
+    unsigned colbits[2];  // bit j: column is interior and inside stage j's region
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
-      const int gx = gxa + o;
-      colok[o] = gx >= 0 && gx <= n - 1;
-      colin[o] = gx >= 1 && gx <= n - 2;
+      const int gx = gxa + o, px = 2 * lane + o;
+      cx[o] = min(max(gx, 0), n - 1);
+      const bool in = gx >= 1 && gx <= n - 2;
+      unsigned b = 0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) b |= (in && px >= j + 1 && px <= BX - 2 - j) ? (1u << j) : 0u;
+      colbits[o] = b;
     }
+    unsigned rowbits[RPW];  // bit j: row is interior and inside stage j's region (uniform)
+    size_t rowoff[RPW];     // clamped row start within a plane (uniform)
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
-      const int gy = gyw + i;
-      rowok[i] = gy >= 0 && gy <= n - 1;
-      rowin[i] = gy >= 1 && gy <= n - 2;
+      const int gy = gyw + i, pr = w * RPW + i;
+      const bool in = gy >= 1 && gy <= n - 2;
+      unsigned b = 0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) b |= (in && pr >= j + 1 && pr <= BY - 2 - j) ? (1u << j) : 0u;
+      rowbits[i] = b;
+      rowoff[i] = (size_t)min(max(gy, 0), n - 1) * (size_t)n;
     }
+    const size_t n2 = (size_t)n * (size_t)n;
 
     T U[Q][RPW][2], F[Q][RPW][2], K[Q][RPW][2];
     T PU[RPW][2], PF[RPW][2], PK[RPW][2];
@@ -96,28 +110,33 @@ struct Tiled {
         for (int o = 0; o < 2; ++o) {
           U[q][i][o] = T(0);
           F[q][i][o] = T(0);
-          if (VAR) K[q][i][o] = T(0);
+          K[q][i][o] = T(0);
         }
 
     auto load = [&](int zl) {
-      const bool zok = zl >= 0 && zl <= n - 1;
+      const size_t zc = (size_t)min(max(zl, 0), n - 1);
 #pragma unroll
-      for (int i = 0; i < RPW; ++i)
+      for (int i = 0; i < RPW; ++i) {
+        const size_t r = zc * n2 + rowoff[i];
+        const T* up = uin + r;
+        const T* fp = f + r;
+        const T* kp = VAR ? k + r : nullptr;
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          const bool ok = zok && rowok[i] && colok[o];
-          const size_t idx = ((size_t)zl * nn + (size_t)(gyw + i)) * nn + (size_t)(gxa + o);
-          T vu = T(0), vf = T(0), vk = T(0);
-          if (ok) {
-            if (!ZERO_IN) vu = uin[idx];
-            vf = f[idx];
-            if (VAR) vk = k[idx];
-          }
-          PU[i][o] = vu;
-          PF[i][o] = vf;
-          if (VAR) PK[i][o] = vk;
+          PU[i][o] = ZERO_IN ? T(0) : up[cx[o]];
+          PF[i][o] = fp[cx[o]];
+          if (VAR) PK[i][o] = kp[cx[o]];
         }
+      }
     };
+
+    // stage j updates plane p only for p in [plo_j, phi_j]
+    int plo[H], phi[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      plo[j] = max(1, z0 - (H - 1 - j));
+      phi[j] = min(n - 2, z1 - 1 + (H - 1 - j));
+    }
 
     const int zbeg = z0 - H, zend = z1 + H;  // planes loaded: [zbeg, zend)
     int zl = zbeg;
@@ -148,29 +167,25 @@ struct Tiled {
 #pragma unroll
       for (int j = 0; j < H; ++j) {
         const int p = zl - 1 - j;
-        const int plo = max(1, z0 - (H - 1 - j)), phi = min(n - 2, z1 - 1 + (H - 1 - j));
-        if (p < plo || p > phi) continue;  // uniform across the workgroup
+        if (p < plo[j] || p > phi[j]) continue;  // uniform across the workgroup
         const int cs = imod(P - 1 - j, Q);  // centre plane p
         const int cm = imod(P - 2 - j, Q);  // plane p - 1
         const int cp = imod(P - j, Q);      // plane p + 1
         const int pslot = imod(p, H);
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
+          if (!((rowbits[i] >> j) & 1u)) continue;  // uniform across the wave
           const int o = (B0 + i + P) & 1;
-          const int pr = w * RPW + i;  // tile row
-          const int px = 2 * lane + o; // tile column
-          const bool act = rowin[i] && colin[o] && pr >= j + 1 && pr <= BY - 2 - j &&
-                           px >= j + 1 && px <= BX - 2 - j;
           // x-neighbours: own other column, or the neighbouring lane's
           T xm, xp, kxm = T(0), kxp = T(0);
           if (o == 0) {
-            xm = __shfl_up(U[cs][i][1], 1, 64);
+            xm = from_lane_below(U[cs][i][1]);
             xp = U[cs][i][1];
-            if (VAR) { kxm = __shfl_up(K[cs][i][1], 1, 64); kxp = K[cs][i][1]; }
+            if (VAR) { kxm = from_lane_below(K[cs][i][1]); kxp = K[cs][i][1]; }
           } else {
             xm = U[cs][i][0];
-            xp = __shfl_down(U[cs][i][0], 1, 64);
-            if (VAR) { kxm = K[cs][i][0]; kxp = __shfl_down(K[cs][i][0], 1, 64); }
+            xp = from_lane_above(U[cs][i][0]);
+            if (VAR) { kxm = K[cs][i][0]; kxp = from_lane_above(K[cs][i][0]); }
           }
           // y-neighbours in column o: own rows, or the adjacent wave's edge row
           T ym = T(0), yp = T(0), kym = T(0), kyp = T(0);
@@ -197,7 +212,8 @@ struct Tiled {
             v = gs_var<T, 3>(h2f, K[cs][i][o], xm, kxm, xp, kxp, ym, kym, yp, kyp, zm,
                              K[cm][i][o], zp, K[cp][i][o]);
           }
-          if (act) U[cs][i][o] = v;
+          const bool act = (colbits[o] >> j) & 1u;
+          U[cs][i][o] = act ? v : U[cs][i][o];
         }
       }
 
@@ -210,13 +226,13 @@ struct Tiled {
         const int pslot = imod(zl - d, H);
         {
           constexpr int i = 0;
-          const int o = (B0 + i + P) & 1;
+          constexpr int o = (B0 + i + P) & 1;
           sh.eu[wb][pslot][w][0][lane] = U[sl][i][o];
           if (VAR) sh.ek[wb][pslot][w][0][lane] = K[sl][i][o];
         }
         {
           constexpr int i = RPW - 1;
-          const int o = (B0 + i + P) & 1;
+          constexpr int o = (B0 + i + P) & 1;
           sh.eu[wb][pslot][w][1][lane] = U[sl][i][o];
           if (VAR) sh.ek[wb][pslot][w][1][lane] = K[sl][i][o];
         }
@@ -228,14 +244,11 @@ struct Tiled {
         constexpr int so = imod(P - H, Q);
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
-          const int pr = w * RPW + i;
-          if (!rowin[i] || pr < H || pr > BY - 1 - H) continue;
-          const size_t base = ((size_t)pout * nn + (size_t)(gyw + i)) * nn + (size_t)gxa;
+          if (!((rowbits[i] >> (H - 1)) & 1u)) continue;
+          T* op = uout + (size_t)pout * n2 + rowoff[i];
 #pragma unroll
-          for (int o = 0; o < 2; ++o) {
-            const int px = 2 * lane + o;
-            if (colin[o] && px >= H && px <= BX - 1 - H) uout[base + o] = U[so][i][o];
-          }
+          for (int o = 0; o < 2; ++o)
+            if ((colbits[o] >> (H - 1)) & 1u) op[cx[o]] = U[so][i][o];
         }
       }
       ++step;
@@ -285,20 +298,51 @@ struct LaunchShape {
   int tiles_x, tiles_y, nchunks, zlen, blocks;
 };
 
+// Workgroups of this kernel that fit on the device at once (CUs x resident per CU),
+// queried once per device.
+template <typename Kernel>
+int resident_capacity(Kernel kernel, int block)
+{
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    cache[dev] = cus * per_cu;
+  }
+  return cache[dev];
+}
+
+// Tiles cover the interior in x and y; z is cut into chunks.  Each chunk costs its length
+// plus 2H warm-up planes, and workgroups run in rounds of `capacity`; the chunk count that
+// minimises (rounds x planes per workgroup) -- the critical path -- is chosen.
 template <typename C>
-LaunchShape shape_for(int n, int target_blocks)
+LaunchShape shape_for(int n, int capacity)
 {
   LaunchShape L;
   const int m = n - 2;
   L.tiles_x = (m + C::TXO - 1) / C::TXO;
   L.tiles_y = (m + C::TYO - 1) / C::TYO;
   const int per = L.tiles_x * L.tiles_y;
-  int chunks = (target_blocks + per - 1) / per;
-  if (chunks < 1) chunks = 1;
-  // keep chunks at least 4H planes deep so the z-halo stays a small overhead
-  const int maxchunks = m / (4 * C::H) > 0 ? m / (4 * C::H) : 1;
-  if (chunks > maxchunks) chunks = maxchunks;
-  L.zlen = (m + chunks - 1) / chunks;
+  const int maxchunks = m / (2 * C::H) > 0 ? m / (2 * C::H) : 1;
+  long long best = -1;
+  L.zlen = m;
+  for (int c = 1; c <= maxchunks; ++c) {
+    const int zlen = (m + c - 1) / c;
+    const int chunks = (m + zlen - 1) / zlen;
+    const long long blocks = (long long)per * chunks;
+    const long long rounds = (blocks + capacity - 1) / capacity;
+    const long long cost = rounds * (zlen + 2 * C::H);
+    if (best < 0 || cost < best) {
+      best = cost;
+      L.zlen = zlen;
+    }
+  }
   L.nchunks = (m + L.zlen - 1) / L.zlen;
   L.blocks = per * L.nchunks;
   return L;
@@ -306,22 +350,20 @@ LaunchShape shape_for(int n, int target_blocks)
 
 template <typename T, bool VAR, int S, int W, int RPW>
 void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
-                bool zero_in, int target_blocks)
+                bool zero_in)
 {
   using C = Tiled<T, VAR, S, W, RPW>;
-  const LaunchShape L = shape_for<C>(n, target_blocks);
+  auto kern = zero_in ? k_rbgs_tiled<T, VAR, S, W, RPW, true> : k_rbgs_tiled<T, VAR, S, W, RPW, false>;
+  const LaunchShape L = shape_for<C>(n, resident_capacity(kern, 64 * W));
   const T h2 = (T)(h * h);
-  if (zero_in)
-    k_rbgs_tiled<T, VAR, S, W, RPW, true><<<L.blocks, 64 * W, 0, s>>>(
-        uin, uout, f, k, n, h2, L.tiles_x, L.tiles_y, L.zlen);
-  else
-    k_rbgs_tiled<T, VAR, S, W, RPW, false><<<L.blocks, 64 * W, 0, s>>>(
-        uin, uout, f, k, n, h2, L.tiles_x, L.tiles_y, L.zlen);
+  kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, n, h2, L.tiles_x, L.tiles_y, L.zlen);
 }
 
 }  // namespace
 
-bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n >= 33; }
+// The per-colour kernel is faster up to 129^3 (a 3D level that small streams too few
+// planes per workgroup to hide the pipeline's start-up).
+bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n > 129; }
 
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
 {
@@ -334,17 +376,16 @@ template <typename T>
 void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
                 int sweeps, bool zero_in)
 {
-  constexpr int kTarget = 512;  // workgroups per launch before z-chunking stops
   // the host asks for 2 sweeps with k only in FP32 (rbgs_tiled_max_sweeps)
   if (sweeps == 2) {
     if (k) {
-      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2, 8, 4>(s, n, h, k, f, uin, uout, zero_in, kTarget);
+      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
     } else {
-      launch_cfg<T, false, 2, 8, 4>(s, n, h, k, f, uin, uout, zero_in, kTarget);
+      launch_cfg<T, false, 2, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
     }
   } else {
-    if (k) launch_cfg<T, true, 1, 8, 4>(s, n, h, k, f, uin, uout, zero_in, kTarget);
-    else launch_cfg<T, false, 1, 8, 4>(s, n, h, k, f, uin, uout, zero_in, kTarget);
+    if (k) launch_cfg<T, true, 1, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
+    else launch_cfg<T, false, 1, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
   }
 }
 

@@ -94,8 +94,8 @@ def gaussian_random_field(dim: int, n: int, seed: int, corr: float = 0.1,
     # window [0, 1] of the box: H-grid indices m/4 .. 3m/4
     lo = m // 4
     g = g[(slice(lo, lo + m // 2 + 1),) * dim]
-    ratio = int(round((n - 1) * H))  # n-grid steps per H-grid step (a power of two)
-    if ratio > 1:
+    ratio = (n - 1) * H  # n-grid steps per H-grid step (>= 1)
+    if abs(ratio - 1.0) > 1e-12:
         pos = np.arange(n, dtype=np.float64) / ratio  # node i of the n-grid in H-grid units
         i0 = np.minimum(np.floor(pos).astype(np.int64), g.shape[0] - 2)
         t = pos - i0
