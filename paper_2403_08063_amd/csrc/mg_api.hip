@@ -190,10 +190,16 @@ bool use_tiled(const mg_ctx* c, int l)
 // fused kernel works out of place and alternates between u and t.  zero_guess: u is known
 // to be 0 (a coarse-grid correction) and is not read.
 template <typename T>
-T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool zero_guess)
+T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool zero_guess,
+          const T* ec = nullptr)
 {
   const Level& L = c->lv[l];
   const int dim = c->g.dim;
+  if (ec && (sweeps == 0 || !use_tiled(c, l) || !mgk::rbgs_tiled_fuses_prolong(sizeof(T)))) {
+    // coarse-grid correction as a separate pass when it cannot ride on a fused sweep
+    mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, u);
+    ec = nullptr;
+  }
   if (sweeps == 0) {
     if (zero_guess) mgk::fill<T>(c->s, L.N, T(0), u);
     return u;
@@ -206,12 +212,13 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
     const int maxsw = mgk::rbgs_tiled_max_sweeps(k != nullptr, sizeof(T));
     while (left > 0) {
       const int sw = left >= maxsw ? maxsw : left;
-      mgk::rbgs_tiled<T>(c->s, L.n, L.h, k, f, cur, other, sw, zero);
+      mgk::rbgs_tiled<T>(c->s, L.n, L.h, k, f, cur, other, sw, zero, ec);
       T* x = cur;
       cur = other;
       other = x;
       left -= sw;
       zero = false;
+      ec = nullptr;
     }
     return cur;
   }
@@ -240,9 +247,9 @@ T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
   if (use_tiled(c, l)) mgk::restrict_residual_tiled<T>(c->s, L.n, L.h, V.k, f, cur, C.f);
   else mgk::restrict_residual<T>(c->s, dim, L.n, L.h, V.k, f, cur, C.f);
   T* ec = cycle<T>(c, l + 1, C.u, C.t, C.f, true);
-  mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, cur);
+  // u += P ec, fused into the first post-smoothing pass on large 3D levels (FP32)
   T* other = cur == u ? t : u;
-  return smooth<T>(c, l, cur, other, f, V.k, c->g.nu2, false);
+  return smooth<T>(c, l, cur, other, f, V.k, c->g.nu2, false, ec);
 }
 
 mg_status read_scalar(mg_ctx* c, const double* dev, double* host)

@@ -1,6 +1,6 @@
 // Cross-lane moves within one 64-lane wavefront, by DPP (data-parallel primitives) on the
 // VALU instead of an LDS permute: wave_shr:1 gives lane l the value of lane l-1,
-// wave_shl:1 the value of lane l+1; lanes without a source lane receive 0.
+// wave_shl:1 the value of lane l+1; lanes without a source lane receive 0 (bound_ctrl).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -12,7 +12,7 @@ constexpr int kDppWaveShr1 = 0x138;  // lane l <- lane l-1
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v)
 {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL>

@@ -353,7 +353,14 @@ int best_zlen(int per_tile_plane_count, int zext, int halo, int capacity, int ma
   return bestz;
 }
 
-constexpr int kW = 8, kRPW = 4;
+// Tile shape: waves per workgroup x rows per wave (tile height = their product).
+#ifndef MG_STREAM_W
+#define MG_STREAM_W 8
+#endif
+#ifndef MG_STREAM_RPW
+#define MG_STREAM_RPW 4
+#endif
+constexpr int kW = MG_STREAM_W, kRPW = MG_STREAM_RPW;
 
 }  // namespace
 
@@ -368,7 +375,8 @@ void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const 
     A a{};
     a.f = f; a.u = u; a.k = k; a.out = fc; a.n = nf; a.ih2 = (T)(1.0 / (h * h));
     a.tiles_x = (m + 61) / 62;
-    a.tiles_y = (m + (kW * kRPW / 2 - 2) - 1) / (kW * kRPW / 2 - 2);
+    constexpr int cy = kW * kRPW / 2 - 2;
+    a.tiles_y = (m + cy - 1) / cy;
     const int per = a.tiles_x * a.tiles_y;
     a.zlen = best_zlen(per, m, 1, capacity_of(kern, 64 * kW), 1 << 30);
     const int blocks = per * ((m + a.zlen - 1) / a.zlen);

@@ -40,6 +40,8 @@ namespace {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
+enum { kInRead = 0, kInZero = 1, kInProlong = 2 };
+
 constexpr int imod(int a, int m) { return ((a % m) + m) % m; }
 
 template <typename T, bool VAR, int S, int W, int RPW>
@@ -58,10 +60,18 @@ struct Tiled {
     T ek[VAR ? 2 : 1][VAR ? H : 1][W][2][64]; // and of k
   };
 
+  // The first column of every lane and the first row of every wave have odd global
+  // indices (tile origins are odd, H and RPW even): the fused prolongation relies on it.
+  static_assert(TXO % 2 == 0 && TYO % 2 == 0 && H % 2 == 0, "odd tile origins");
+
   // B0 = parity of (global x of column 0) + (global y of row 0) + z0 - 1 (see below).
-  template <int B0, bool ZERO_IN>
+  // IN: how the input is formed -- kInRead: uin; kInZero: 0 (uin not read);
+  // kInProlong: uin + P ec, the coarse-grid correction ec (nc nodes per side) interpolated
+  // with the same weights and summation order as the stand-alone prolongation kernel.
+  template <int B0, int IN>
   __device__ __forceinline__ static void run(const T* __restrict__ uin, T* __restrict__ uout,
                                              const T* __restrict__ f, const T* __restrict__ k,
+                                             const T* __restrict__ ec, int nc,
                                              int n, T h2, int ox, int oy, int z0, int z1,
                                              Shared& sh)
   {
@@ -113,8 +123,48 @@ struct Tiled {
           K[q][i][o] = T(0);
         }
 
+    // Fused prolongation: coarse column cxa = (gxa - 1) / 2 and cxa + 1, coarse rows
+    // cya .. cya + RPW/2 with cya = (gyw - 1) / 2, and the coarse planes floor(zl/2) (EA) and
+    // floor(zl/2) + 1 (EB), all clamped into the coarse grid.
+    constexpr int CR = RPW / 2 + 1;
+    T EA[CR][2], EB[CR][2];
+    int ccx[2];
+    size_t crow[CR];
+    if (IN == kInProlong) {
+      const int cxa = (gxa - 1) >> 1;
+      ccx[0] = min(max(cxa, 0), nc - 1);
+      ccx[1] = min(max(cxa + 1, 0), nc - 1);
+      const int cya = (gyw - 1) >> 1;
+#pragma unroll
+      for (int r = 0; r < CR; ++r) crow[r] = (size_t)min(max(cya + r, 0), nc - 1) * (size_t)nc;
+    }
+    const size_t nc2 = (size_t)nc * (size_t)nc;
+    auto load_coarse = [&](T (&E)[CR][2], int cz) {
+      const size_t zo = (size_t)min(max(cz, 0), nc - 1) * nc2;
+#pragma unroll
+      for (int r = 0; r < CR; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) E[r][c] = ec[zo + crow[r] + ccx[c]];
+    };
+    bool first_load = true;
+
     auto load = [&](int zl) {
       const size_t zc = (size_t)min(max(zl, 0), n - 1);
+      if constexpr (IN == kInProlong) {
+        // keep EA = plane floor(zl/2), EB = plane floor(zl/2) + 1 (needed for odd zl)
+        if (first_load) {
+          load_coarse(EA, zl >> 1);
+          load_coarse(EB, (zl >> 1) + 1);
+          first_load = false;
+        } else if (zl & 1) {
+          load_coarse(EB, (zl >> 1) + 1);
+        } else {
+#pragma unroll
+          for (int r = 0; r < CR; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) EA[r][c] = EB[r][c];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
         const size_t r = zc * n2 + rowoff[i];
@@ -123,11 +173,53 @@ struct Tiled {
         const T* kp = VAR ? k + r : nullptr;
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          PU[i][o] = ZERO_IN ? T(0) : up[cx[o]];
+          PU[i][o] = IN == kInZero ? T(0) : up[cx[o]];
           PF[i][o] = fp[cx[o]];
           if (VAR) PK[i][o] = kp[cx[o]];
         }
       }
+    };
+
+    // Plane zl enters the queue one step after its loads were issued, so that no arithmetic
+    // waits on them early; in kInProlong it gains the interpolated coarse-grid correction
+    // P ec on interior nodes (coarse rows of a fine row
+    // i: i/2, i/2+1 for even i (odd fine y), (i+1)/2 for odd i; coarse columns cxa, cxa+1 for
+    // column 0 (odd fine x), cxa+1 for column 1; coarse planes EA (and EB for odd zl)).
+    auto insert = [&](int zl, auto S0C) {
+      constexpr int s0 = decltype(S0C)::value;
+      const bool zin = zl >= 1 && zl <= n - 2;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          T v = PU[i][o];
+          if constexpr (IN == kInProlong) {
+            const int mz = (zl & 1) ? 2 : 1;
+            const T wz = (zl & 1) ? T(0.5) : T(1);
+            const int my = (i % 2 == 0) ? 2 : 1;
+            const int rb = (i % 2 == 0) ? i / 2 : (i + 1) / 2;
+            const T wy = (i % 2 == 0) ? T(0.5) : T(1);
+            const int mx = o == 0 ? 2 : 1;
+            const int cb = o == 0 ? 0 : 1;
+            const T wx = o == 0 ? T(0.5) : T(1);
+            T sum = T(0);
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) {
+              if (a2 >= mz) break;
+#pragma unroll
+              for (int b2 = 0; b2 < my; ++b2)
+#pragma unroll
+                for (int c2 = 0; c2 < mx; ++c2)
+                  sum = sum + (wz * wy * wx) * (a2 == 0 ? EA[rb + b2][cb + c2] : EB[rb + b2][cb + c2]);
+            }
+            const bool in = zin && gyw + i >= 1 && gyw + i <= n - 2 && gxa + o >= 1 &&
+                            gxa + o <= n - 2;
+            if (in) v = v + sum;
+          }
+          U[s0][i][o] = v;
+          F[s0][i][o] = PF[i][o];
+          if (VAR) K[s0][i][o] = PK[i][o];
+        }
     };
 
     // stage j updates plane p only for p in [plo_j, phi_j]
@@ -151,14 +243,7 @@ struct Tiled {
       constexpr int P = decltype(PC)::value;
       constexpr int s0 = imod(P, Q);
       // the prefetched plane zl enters the queue
-#pragma unroll
-      for (int i = 0; i < RPW; ++i)
-#pragma unroll
-        for (int o = 0; o < 2; ++o) {
-          U[s0][i][o] = PU[i][o];
-          F[s0][i][o] = PF[i][o];
-          if (VAR) K[s0][i][o] = PK[i][o];
-        }
+      insert(zl, IC<s0>{});
       __syncthreads();
       if (zl + 1 < zend) load(zl + 1);
       const int rb = (step + 1) & 1;  // LDS buffer written in the previous step
@@ -269,10 +354,11 @@ struct Tiled {
   }
 };
 
-template <typename T, bool VAR, int S, int W, int RPW, bool ZERO_IN>
+template <typename T, bool VAR, int S, int W, int RPW, int IN>
 __global__ void __launch_bounds__(64 * W)
     k_rbgs_tiled(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
-                 const T* __restrict__ k, int n, T h2, int tiles_x, int tiles_y, int zlen)
+                 const T* __restrict__ k, const T* __restrict__ ec, int nc, int n, T h2,
+                 int tiles_x, int tiles_y, int zlen)
 {
   using C = Tiled<T, VAR, S, W, RPW>;
   __shared__ typename C::Shared sh;
@@ -290,8 +376,8 @@ __global__ void __launch_bounds__(64 * W)
   // parity of (x of column 0) + (y of row 0) + z0 - 1; RPW is even, so it is the same
   // for every wave's first row
   const int b0 = ((ox - C::H) + (oy - C::H) + z0 - 1) & 1;
-  if (b0) C::template run<1, ZERO_IN>(uin, uout, f, k, n, h2, ox, oy, z0, z1, sh);
-  else C::template run<0, ZERO_IN>(uin, uout, f, k, n, h2, ox, oy, z0, z1, sh);
+  if (b0) C::template run<1, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, sh);
+  else C::template run<0, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, sh);
 }
 
 struct LaunchShape {
@@ -348,15 +434,27 @@ LaunchShape shape_for(int n, int capacity)
   return L;
 }
 
-template <typename T, bool VAR, int S, int W, int RPW>
-void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
-                bool zero_in)
+template <typename T, bool VAR, int S, int W, int RPW, int IN>
+void launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
+               const T* ec)
 {
   using C = Tiled<T, VAR, S, W, RPW>;
-  auto kern = zero_in ? k_rbgs_tiled<T, VAR, S, W, RPW, true> : k_rbgs_tiled<T, VAR, S, W, RPW, false>;
+  auto kern = k_rbgs_tiled<T, VAR, S, W, RPW, IN>;
   const LaunchShape L = shape_for<C>(n, resident_capacity(kern, 64 * W));
   const T h2 = (T)(h * h);
-  kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, n, h2, L.tiles_x, L.tiles_y, L.zlen);
+  const int nc = (n - 1) / 2 + 1;
+  kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, L.tiles_x, L.tiles_y, L.zlen);
+}
+
+template <typename T, bool VAR, int S, int W, int RPW>
+void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
+                bool zero_in, const T* ec)
+{
+  if (ec) {
+    // only FP32 passes fuse the prolongation (rbgs_tiled_fuses_prolong)
+    if constexpr (sizeof(T) == 4) launch_in<T, VAR, S, W, RPW, kInProlong>(s, n, h, k, f, uin, uout, ec);
+  } else if (zero_in) launch_in<T, VAR, S, W, RPW, kInZero>(s, n, h, k, f, uin, uout, ec);
+  else launch_in<T, VAR, S, W, RPW, kInRead>(s, n, h, k, f, uin, uout, ec);
 }
 
 }  // namespace
@@ -365,6 +463,12 @@ void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T*
 // planes per workgroup to hide the pipeline's start-up).
 bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n > 129; }
 
+bool rbgs_tiled_fuses_prolong(size_t value_bytes)
+{
+  // FP64 passes holding the coarse-grid correction as well exceed the register file
+  return value_bytes == 4;
+}
+
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
 {
   // the FP64 variable-coefficient pass keeps k in registers too: one sweep per pass keeps
@@ -372,26 +476,35 @@ int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
   return (var && value_bytes == 8) ? 1 : 2;
 }
 
+// Tile shape: waves per workgroup x rows per wave (tile height = their product).
+#ifndef MG_SMOOTH_W
+#define MG_SMOOTH_W 8
+#endif
+#ifndef MG_SMOOTH_RPW
+#define MG_SMOOTH_RPW 4
+#endif
+constexpr int kSW = MG_SMOOTH_W, kSR = MG_SMOOTH_RPW;
+
 template <typename T>
 void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
-                int sweeps, bool zero_in)
+                int sweeps, bool zero_in, const T* ec)
 {
   // the host asks for 2 sweeps with k only in FP32 (rbgs_tiled_max_sweeps)
   if (sweeps == 2) {
     if (k) {
-      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
+      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
     } else {
-      launch_cfg<T, false, 2, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
+      launch_cfg<T, false, 2, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
     }
   } else {
-    if (k) launch_cfg<T, true, 1, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
-    else launch_cfg<T, false, 1, 8, 4>(s, n, h, k, f, uin, uout, zero_in);
+    if (k) launch_cfg<T, true, 1, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
+    else launch_cfg<T, false, 1, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
   }
 }
 
 template void rbgs_tiled<double>(hipStream_t, int, double, const double*, const double*,
-                                 const double*, double*, int, bool);
+                                 const double*, double*, int, bool, const double*);
 template void rbgs_tiled<float>(hipStream_t, int, double, const float*, const float*,
-                                const float*, float*, int, bool);
+                                const float*, float*, int, bool, const float*);
 
 }  // namespace mgk
