@@ -17,6 +17,13 @@ Also reported:
     residual norm, scaled by the FP64 cycle count).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--n 513]
+
+HBM traffic of the fine-level smoother (two counter runs, then a summary):
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py --pmc-sample
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o pmc -- python bench.py --pmc-sample
+  python bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write
+--pmc-sample runs a plain device copy of 1 GiB (the calibration: its counters must read
+1 GiB fetched and 1 GiB written) and 10 launches of the fused FP64 smoother at 513^3.
 """
 from __future__ import annotations
 
@@ -60,6 +67,69 @@ def measured_traffic(interior_nodes: int):
     return rec.get("bytes_per_launch")
 
 
+CALIB_BYTES = 1 << 30
+
+
+def pmc_sample(n: int):
+    """Workload profiled by the counter runs: a calibration copy, then the smoother."""
+    import torch
+
+    from paper_2403_08063_amd import Multigrid, inputs
+
+    dev = torch.device("cuda:0")
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    levels = (n - 1).bit_length() - 1
+    f = torch.from_numpy(inputs.uniform_interior(3, n, seed=3)).to(dev)
+    u = torch.zeros_like(f)
+    mg = Multigrid(3, n, levels, precision="f64", device=dev)
+    mg.smooth(0, f, u, 20)
+    torch.cuda.synchronize()
+    print("pmc sample done", file=sys.stderr)
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, n: int):
+    """Per-launch HBM bytes of the fused FP64 smoother from the two counter runs, each
+    counter scaled so that the calibration copy reads exactly its known size."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        rows = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return rows
+
+    out = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = per_kernel(d, counter)
+        copy = [v for name, v in rows if "copy" in name.lower() and "fill" not in name.lower()]
+        smooth = [v for name, v in rows if SMOOTHER_KERNEL in name and "double" in name]
+        if not copy or not smooth:
+            raise SystemExit(f"{counter}: no calibration copy or smoother dispatch in {d}")
+        calib = copy[0]  # KiB the counter reads for the 1 GiB calibration copy
+        factor = (CALIB_BYTES / 1024.0) / calib
+        out[key] = {"counter_kib_per_launch": sum(smooth) / len(smooth),
+                    "calibration_kib": calib, "scale": factor,
+                    "bytes_per_launch": sum(smooth) / len(smooth) * 1024.0 * factor,
+                    "launches": len(smooth)}
+    rec = {
+        "kernel": f"{SMOOTHER_KERNEL}<double, 2 sweeps>", "n": n,
+        "source_sha256_16": source_hash(SMOOTHER_SOURCE),
+        "fetch": out["fetch"], "write": out["write"],
+        "bytes_per_launch": out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"],
+        "algorithmic_bytes_per_launch": 24 * (n - 2) ** 3,
+    }
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(f_np, levels, fp64_cycles):
     import numpy as np
 
@@ -92,7 +162,15 @@ def main():
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-sample", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.n)
+        return
+    if args.pmc_sample:
+        pmc_sample(args.n)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
               "multi-GPU path; see the sharding design in DESIGN.md", file=sys.stderr)
