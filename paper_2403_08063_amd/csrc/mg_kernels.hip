@@ -85,30 +85,35 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ------------------------------------------------------------------ prolongation
-// u += P e at fine interior node (z, y, x); along each axis an even index 2I takes coarse
-// I with weight 1, an odd index 2I+1 takes I and I+1 with weight 1/2; the terms are summed
-// in the loop order z, y, x.
+// u += P e on fine interior nodes; along each axis an even index 2I takes coarse I with
+// weight 1, an odd index 2I+1 takes I and I+1 with weight 1/2; the terms are summed in the
+// loop order z, y, x.  Thread c of a fine row handles the pair x = 2c-1 (coarse c-1, c)
+// and x = 2c (coarse c), which share the two coarse values of each coarse row.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock)
     k_prolong_add(const T* __restrict__ e, T* __restrict__ u, int nc)
 {
   const int nf = 2 * (nc - 1) + 1;
-  const int x = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = 1 + blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y + 1;
   const int z = DIM == 3 ? (int)blockIdx.z + 1 : 0;
-  if (x > nf - 2) return;
-  const int mz = DIM == 3 ? 1 + (z & 1) : 1, my = 1 + (y & 1), mx = 1 + (x & 1);
-  const int cz0 = DIM == 3 ? z >> 1 : 0, cy0 = y >> 1, cx0 = x >> 1;
+  if (c > nc - 1) return;
+  const int mz = DIM == 3 ? 1 + (z & 1) : 1, my = 1 + (y & 1);
+  const int cz0 = DIM == 3 ? z >> 1 : 0, cy0 = y >> 1;
   const T wz = DIM == 3 ? ((z & 1) ? T(0.5) : T(1)) : T(1);
   const T wy = (y & 1) ? T(0.5) : T(1);
-  const T wx = (x & 1) ? T(0.5) : T(1);
-  T s = T(0);
+  T sodd = T(0), seven = T(0);  // x = 2c-1 and x = 2c
   for (int a = 0; a < mz; ++a)
-    for (int b = 0; b < my; ++b)
-      for (int c = 0; c < mx; ++c)
-        s = s + (wz * wy * wx) * e[((size_t)(cz0 + a) * nc + (cy0 + b)) * (size_t)nc + (cx0 + c)];
-  const size_t i = ((size_t)z * nf + y) * (size_t)nf + x;
-  u[i] = u[i] + s;
+    for (int b = 0; b < my; ++b) {
+      const size_t row = ((size_t)(cz0 + a) * nc + (cy0 + b)) * (size_t)nc;
+      const T e0 = e[row + c - 1], e1 = e[row + c];
+      sodd = sodd + (wz * wy * T(0.5)) * e0;
+      sodd = sodd + (wz * wy * T(0.5)) * e1;
+      seven = seven + (wz * wy * T(1)) * e1;
+    }
+  const size_t i = ((size_t)z * nf + y) * (size_t)nf + (2 * c - 1);
+  u[i] = u[i] + sodd;
+  if (2 * c <= nf - 2) u[i + 1] = u[i + 1] + seven;
 }
 
 // ------------------------------------------------------------------ coarsest level
@@ -520,7 +525,7 @@ template <typename T>
 void prolong_add(hipStream_t s, int dim, int nc, const T* ec, T* u)
 {
   const int nf = 2 * (nc - 1) + 1;
-  const int cnt = nf - 2;
+  const int cnt = nc - 1;  // fine x pairs per row
   const int bx = cnt >= 256 ? 256 : (cnt > 64 ? 128 : 64);
   const dim3 grid(cdiv(cnt, bx), nf - 2, dim == 3 ? nf - 2 : 1);
   if (dim == 3) k_prolong_add<T, 3><<<grid, bx, 0, s>>>(ec, u, nc);

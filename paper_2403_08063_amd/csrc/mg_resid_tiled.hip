@@ -353,14 +353,13 @@ int best_zlen(int per_tile_plane_count, int zext, int halo, int capacity, int ma
   return bestz;
 }
 
-// Tile shape: waves per workgroup x rows per wave (tile height = their product).
-#ifndef MG_STREAM_W
-#define MG_STREAM_W 8
-#endif
-#ifndef MG_STREAM_RPW
-#define MG_STREAM_RPW 4
-#endif
-constexpr int kW = MG_STREAM_W, kRPW = MG_STREAM_RPW;
+// Tile shapes (waves per workgroup x rows per wave), per pass, from timing sweeps on MI355X
+// at 513^3: the restriction keeps 4 rows per wave (its coarse rows pair fine rows), the
+// norm and the refinement pass favour more, lighter waves.
+constexpr int kW = 8, kRPW = 4;          // restriction
+constexpr int kNW = 8, kNRPW = 2;        // norm
+constexpr int kRW = 16, kRRPW = 2;       // refinement pass
+constexpr int kRVW = 8;                  // ... with variable k (16 waves would spill registers)
 
 }  // namespace
 
@@ -387,20 +386,20 @@ void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const 
 }
 
 namespace {
-template <bool VAR, int MODE>
-void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, kW, kRPW>::Args a, double* partial,
+template <bool VAR, int MODE, int W, int RPW>
+void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, W, RPW>::Args a, double* partial,
                  double* out)
 {
-  using C = Stream<double, VAR, MODE, kW, kRPW>;
-  auto kern = k_stream<double, VAR, MODE, kW, kRPW>;
+  using C = Stream<double, VAR, MODE, W, RPW>;
+  auto kern = k_stream<double, VAR, MODE, W, RPW>;
   const int m = a.n - 2;
   a.tiles_x = (m + C::OX - 1) / C::OX;
   a.tiles_y = (m + C::OY - 1) / C::OY;
   const int per = a.tiles_x * a.tiles_y;
-  a.zlen = best_zlen(per, m, 2, capacity_of(kern, 64 * kW), kStreamPartials);
+  a.zlen = best_zlen(per, m, 2, capacity_of(kern, 64 * W), kStreamPartials);
   const int blocks = per * ((m + a.zlen - 1) / a.zlen);
   a.partial = partial;
-  kern<<<blocks, 64 * kW, 0, s>>>(a);
+  kern<<<blocks, 64 * W, 0, s>>>(a);
   k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
 }
 }  // namespace
@@ -409,13 +408,13 @@ void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const do
                        const double* u, int mode, double* partial, double* out)
 {
   if (k) {
-    Stream<double, true, kNorm, kW, kRPW>::Args a{};
+    Stream<double, true, kNorm, kNW, kNRPW>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
-    launch_fine<true, kNorm>(s, a, partial, out);
+    launch_fine<true, kNorm, kNW, kNRPW>(s, a, partial, out);
   } else {
-    Stream<double, false, kNorm, kW, kRPW>::Args a{};
+    Stream<double, false, kNorm, kNW, kNRPW>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
-    launch_fine<false, kNorm>(s, a, partial, out);
+    launch_fine<false, kNorm, kNW, kNRPW>(s, a, partial, out);
   }
 }
 
@@ -424,15 +423,15 @@ void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double
                    float* r32, double* partial, double* out)
 {
   if (k) {
-    Stream<double, true, kRefine, kW, kRPW>::Args a{};
+    Stream<double, true, kRefine, kRVW, kRRPW>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
     a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
-    launch_fine<true, kRefine>(s, a, partial, out);
+    launch_fine<true, kRefine, kRVW, kRRPW>(s, a, partial, out);
   } else {
-    Stream<double, false, kRefine, kW, kRPW>::Args a{};
+    Stream<double, false, kRefine, kRW, kRRPW>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
     a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
-    launch_fine<false, kRefine>(s, a, partial, out);
+    launch_fine<false, kRefine, kRW, kRRPW>(s, a, partial, out);
   }
 }
 
