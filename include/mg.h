@@ -150,10 +150,12 @@ mg_status mg_coarsest_solve(mg_ctx* ctx, const double* f, double* u);
  * fixed order (bitwise reproducible).  Synchronises the stream. */
 mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, double* norm2);
 
-/* Smoother implementation switch (diagnostics and tests): fused = 1 (default) uses the
- * temporally blocked out-of-place kernel on large 3D levels, fused = 0 the per-colour
- * in-place kernel everywhere.  Both give bitwise-identical results. */
-mg_status mg_set_fused_smoother(mg_ctx* ctx, int fused);
+/* Kernel-fusion switch (diagnostics and tests).  enable = 1 (default): the temporally
+ * blocked out-of-place smoother on large 3D levels and the one-launch coarse tail of the
+ * V-cycle (all levels with at most 4096 interior nodes); enable = 0: the per-colour
+ * smoother and one launch per step everywhere.  Smoothing results are bitwise identical
+ * either way, and so is the coarse tail. */
+mg_status mg_set_fusion(mg_ctx* ctx, int enable);
 
 /* Message for the last failing call on ctx, or for the last failing mg_setup /
  * mg_validate call of this thread when ctx is NULL.  Never NULL. */

@@ -22,7 +22,7 @@ EXPORTS = [
     "mg_solve", "mg_solve_adjoint", "mg_grad", "mg_smooth", "mg_smooth_f32", "mg_residual",
     "mg_restrict_residual", "mg_restrict_residual_f32", "mg_prolong_correct",
     "mg_prolong_correct_f32", "mg_coarsest_solve", "mg_residual_norm2",
-    "mg_set_fused_smoother", "mg_last_error", "mg_destroy",
+    "mg_set_fusion", "mg_last_error", "mg_destroy",
 ]
 
 
@@ -71,7 +71,7 @@ def lib() -> ctypes.CDLL:
         "mg_prolong_correct_f32": (i, [P, i, P, P]),
         "mg_coarsest_solve": (i, [P, P, P]),
         "mg_residual_norm2": (i, [P, P, P, PD]),
-        "mg_set_fused_smoother": (i, [P, i]),
+        "mg_set_fusion": (i, [P, i]),
         "mg_last_error": (ctypes.c_char_p, [P]),
         "mg_destroy": (None, [P]),
     }

@@ -48,6 +48,7 @@ struct mg_ctx {
   double* scal = nullptr;  // device scalars: [0] norm2, [1] rhs norm2
   bool coeffs = false;
   bool fused = true;
+  int tail_first = -1;  // first level handled by the one-launch coarse tail (-1: none)
   char err[512] = "no error";
 };
 
@@ -238,6 +239,21 @@ T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
   const int dim = c->g.dim;
   const Level& L = c->lv[l];
   const View<T> V = view<T>(c, l);
+  if (c->fused && l == c->tail_first && zero_guess && u == V.u && f == V.f) {
+    // levels l .. coarsest in one launch (same arithmetic as the per-level kernels)
+    mgk::TailArgs<T> a{};
+    a.nlev = c->g.levels - l;
+    a.nu1 = c->g.nu1;
+    a.nu2 = c->g.nu2;
+    a.ainv = c->ainv;
+    for (int q = 0; q < a.nlev; ++q) {
+      const View<T> W = view<T>(c, l + q);
+      const double h = c->lv[l + q].h;
+      a.lv[q] = {W.u, W.f, W.k, c->lv[l + q].n, (T)(h * h), (T)(1.0 / (h * h))};
+    }
+    mgk::tail_cycle<T>(c->s, dim, a);
+    return u;
+  }
   if (l == c->g.levels - 1) {
     mgk::coarsest_solve<T>(c->s, dim, L.n, c->ainv, f, u);
     return u;
@@ -462,6 +478,11 @@ mg_status mg_setup(const mg_grid* grid, void* workspace, size_t bytes, void* str
   c->s = static_cast<hipStream_t>(stream);
   Carver cv{static_cast<char*>(workspace)};
   layout(grid, cv, c);
+  for (int l = 1; l + 1 < grid->levels && l - 1 < mgk::kMaxTail; ++l)
+    if (mgk::tail_fits(grid->dim, c->lv[l].n) && grid->levels - l <= mgk::kMaxTail) {
+      c->tail_first = l;
+      break;
+    }
   // zero the whole workspace once: coarse boundaries (zero Dirichlet data of corrections)
   // and the boundaries of the second buffers are never written afterwards
   mgk::fill<double>(c->s, need / sizeof(double), 0.0, static_cast<double*>(workspace));
@@ -609,10 +630,10 @@ mg_status mg_residual_norm2(mg_ctx* c, const double* f, const double* u, double*
   return read_scalar(c, c->scal, out);
 }
 
-mg_status mg_set_fused_smoother(mg_ctx* c, int fused)
+mg_status mg_set_fusion(mg_ctx* c, int enable)
 {
   if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
-  c->fused = fused != 0;
+  c->fused = enable != 0;
   return MG_OK;
 }
 

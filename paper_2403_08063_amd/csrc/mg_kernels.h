@@ -89,6 +89,29 @@ void cast_to_f32(hipStream_t s, size_t count, const double* src, float* dst);
 void grad(hipStream_t s, int dim, int n, const double* u, const double* lam, double* dk,
           double* df);
 
+// Coarse tail (mg_tail.hip): one workgroup runs the whole V-cycle on levels
+// lv[0] .. lv[nlev-1] (the last one the coarsest, solved with ainv) from a zero guess on
+// every level; lv[0].f is the right-hand side, lv[0].u receives the result.
+constexpr int kTailMaxNodes = 4096;  // interior nodes of the finest tail level
+constexpr int kMaxTail = 16;
+template <typename T>
+struct TailLevel {
+  T* u;
+  T* f;
+  const T* k;  // nullptr: constant coefficient
+  int n;
+  T h2, ih2;   // h^2 and 1/h^2 of the level, as the per-level kernels round them
+};
+template <typename T>
+struct TailArgs {
+  TailLevel<T> lv[kMaxTail];
+  int nlev, nu1, nu2;
+  const double* ainv;
+};
+bool tail_fits(int dim, int n);
+template <typename T>
+void tail_cycle(hipStream_t s, int dim, const TailArgs<T>& a);
+
 template <typename T>
 void fill(hipStream_t s, size_t count, T value, T* p);
 template <typename T>

@@ -17,11 +17,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ bool interior3(int n, int z, int y, int x)
-{
-  return x >= 1 && x <= n - 2 && y >= 1 && y <= n - 2 && z >= 1 && z <= n - 2;
-}
-
 // ------------------------------------------------------------------ red-black half-sweep
 // Thread t of row (y, z) updates the t-th node of the colour in that row:
 // x = x0 + 2t with x0 the first interior x of the colour.
@@ -57,9 +52,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ------------------------------------------------------------------ residual + restriction
-// One thread per coarse interior node: the 3^d fine residuals around 2I are formed and
-// combined with the full-weighting weights prod_a w(o_a), w(0) = 1/2, w(+-1) = 1/4, in
-// the loop order z, y, x.
+// One thread per coarse interior node (restrict_at).
 template <typename T, int DIM, bool VAR>
 __global__ void __launch_bounds__(kBlock)
     k_restrict_residual(const T* __restrict__ f, const T* __restrict__ u,
@@ -70,61 +63,24 @@ __global__ void __launch_bounds__(kBlock)
   const int Y = blockIdx.y + 1;
   const int Z = DIM == 3 ? (int)blockIdx.z + 1 : 0;
   if (X > nc - 2) return;
-  const size_t sy = (size_t)nf, sz = (size_t)nf * nf;
-  const T w[3] = {T(0.25), T(0.5), T(0.25)};
-  T s = T(0);
-  for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        const int fz = DIM == 3 ? 2 * Z + oz : 0;
-        const size_t i = ((size_t)fz * nf + (2 * Y + oy)) * (size_t)nf + (2 * X + ox);
-        const T wt = w[ox + 1] * w[oy + 1] * (DIM == 3 ? w[oz + 1] : T(1));
-        s = s + wt * resid_at<T, DIM, VAR>(f, u, k, i, sy, sz, ih2);
-      }
-  fc[((size_t)Z * nc + Y) * (size_t)nc + X] = s;
+  fc[((size_t)Z * nc + Y) * (size_t)nc + X] = restrict_at<T, DIM, VAR>(f, u, k, nf, ih2, X, Y, Z);
 }
 
 // ------------------------------------------------------------------ prolongation
-// u += P e on fine interior nodes; along each axis an even index 2I takes coarse I with
-// weight 1, an odd index 2I+1 takes I and I+1 with weight 1/2; the terms are summed in the
-// loop order z, y, x.  Thread c of a fine row handles the pair x = 2c-1 (coarse c-1, c)
-// and x = 2c (coarse c), which share the two coarse values of each coarse row.
+// Thread c of a fine row handles the pair x = 2c-1 (coarse c-1, c) and x = 2c (coarse c),
+// which share the two coarse values of each coarse row (prolong_pair).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock)
     k_prolong_add(const T* __restrict__ e, T* __restrict__ u, int nc)
 {
-  const int nf = 2 * (nc - 1) + 1;
   const int c = 1 + blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y + 1;
   const int z = DIM == 3 ? (int)blockIdx.z + 1 : 0;
   if (c > nc - 1) return;
-  const int mz = DIM == 3 ? 1 + (z & 1) : 1, my = 1 + (y & 1);
-  const int cz0 = DIM == 3 ? z >> 1 : 0, cy0 = y >> 1;
-  const T wz = DIM == 3 ? ((z & 1) ? T(0.5) : T(1)) : T(1);
-  const T wy = (y & 1) ? T(0.5) : T(1);
-  T sodd = T(0), seven = T(0);  // x = 2c-1 and x = 2c
-  for (int a = 0; a < mz; ++a)
-    for (int b = 0; b < my; ++b) {
-      const size_t row = ((size_t)(cz0 + a) * nc + (cy0 + b)) * (size_t)nc;
-      const T e0 = e[row + c - 1], e1 = e[row + c];
-      sodd = sodd + (wz * wy * T(0.5)) * e0;
-      sodd = sodd + (wz * wy * T(0.5)) * e1;
-      seven = seven + (wz * wy * T(1)) * e1;
-    }
-  const size_t i = ((size_t)z * nf + y) * (size_t)nf + (2 * c - 1);
-  u[i] = u[i] + sodd;
-  if (2 * c <= nf - 2) u[i + 1] = u[i + 1] + seven;
+  prolong_pair<T, DIM>(e, u, nc, c, y, z);
 }
 
 // ------------------------------------------------------------------ coarsest level
-// Interior unknown q of the coarsest level <-> node (z, y, x) in lexicographic order.
-__device__ __forceinline__ void unknown_to_node(int dim, int n, int q, int& z, int& y, int& x)
-{
-  const int m1 = n - 2;
-  x = 1 + q % m1;
-  y = 1 + (q / m1) % m1;
-  z = dim == 3 ? 1 + q / (m1 * m1) : 0;
-}
 
 // One workgroup: assemble A (m x m, row-major) in `a`, Cholesky-factor it in place
 // (right-looking: scale column j, then update the trailing lower triangle), then form
@@ -193,29 +149,14 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// One workgroup: b = interior of f (in double), u_q = sum_c ainv[c][q] b_c (ainv is
-// symmetric; column access keeps the reads of a wavefront contiguous).
+// One workgroup: interior of u = ainv * interior of f (coarsest_apply).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_coarsest_solve(int dim, int n, const double* __restrict__ ainv, const T* __restrict__ f,
                      T* __restrict__ u)
 {
   __shared__ double b[1024];
-  const int m1 = n - 2;
-  const int m = dim == 3 ? m1 * m1 * m1 : m1 * m1;
-  for (int q = threadIdx.x; q < m; q += blockDim.x) {
-    int z, y, x;
-    unknown_to_node(dim, n, q, z, y, x);
-    b[q] = (double)f[((size_t)z * n + y) * (size_t)n + x];
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < m; q += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < m; ++c) s += ainv[(size_t)c * m + q] * b[c];
-    int z, y, x;
-    unknown_to_node(dim, n, q, z, y, x);
-    u[((size_t)z * n + y) * (size_t)n + x] = (T)s;
-  }
+  coarsest_apply<T>(dim, n, ainv, f, u, b);
 }
 
 // ------------------------------------------------------------------ reductions

@@ -121,4 +121,87 @@ __device__ __forceinline__ T gs_at(const T* __restrict__ f, const T* u, const T*
                         zm, kzm, zp, kzp);
 }
 
+// Full weighting of the fine residual around coarse interior node (X, Y, Z): the 3^d fine
+// residuals around 2I combined with weights prod_a w(o_a), w(0) = 1/2, w(+-1) = 1/4, summed
+// in the loop order z, y, x.
+template <typename T, int DIM, bool VAR>
+__device__ __forceinline__ T restrict_at(const T* __restrict__ f, const T* __restrict__ u,
+                                         const T* __restrict__ k, int nf, T ih2, int X, int Y,
+                                         int Z)
+{
+  const size_t sy = (size_t)nf, sz = (size_t)nf * nf;
+  const T w[3] = {T(0.25), T(0.5), T(0.25)};
+  T s = T(0);
+  for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int fz = DIM == 3 ? 2 * Z + oz : 0;
+        const size_t i = ((size_t)fz * nf + (2 * Y + oy)) * (size_t)nf + (2 * X + ox);
+        const T wt = w[ox + 1] * w[oy + 1] * (DIM == 3 ? w[oz + 1] : T(1));
+        s = s + wt * resid_at<T, DIM, VAR>(f, u, k, i, sy, sz, ih2);
+      }
+  return s;
+}
+
+// u += P e for the fine pair x = 2c-1, 2c of row (y, z), c in 1..nc-1: along each axis an
+// even index 2I takes coarse I with weight 1, an odd index 2I+1 takes I and I+1 with weight
+// 1/2; terms summed in the loop order z, y, x.
+template <typename T, int DIM>
+__device__ __forceinline__ void prolong_pair(const T* __restrict__ e, T* __restrict__ u, int nc,
+                                             int c, int y, int z)
+{
+  const int nf = 2 * (nc - 1) + 1;
+  const int mz = DIM == 3 ? 1 + (z & 1) : 1, my = 1 + (y & 1);
+  const int cz0 = DIM == 3 ? z >> 1 : 0, cy0 = y >> 1;
+  const T wz = DIM == 3 ? ((z & 1) ? T(0.5) : T(1)) : T(1);
+  const T wy = (y & 1) ? T(0.5) : T(1);
+  T sodd = T(0), seven = T(0);  // x = 2c-1 and x = 2c
+  for (int a = 0; a < mz; ++a)
+    for (int b = 0; b < my; ++b) {
+      const size_t row = ((size_t)(cz0 + a) * nc + (cy0 + b)) * (size_t)nc;
+      const T e0 = e[row + c - 1], e1 = e[row + c];
+      sodd = sodd + (wz * wy * T(0.5)) * e0;
+      sodd = sodd + (wz * wy * T(0.5)) * e1;
+      seven = seven + (wz * wy * T(1)) * e1;
+    }
+  const size_t i = ((size_t)z * nf + y) * (size_t)nf + (2 * c - 1);
+  u[i] = u[i] + sodd;
+  if (2 * c <= nf - 2) u[i + 1] = u[i + 1] + seven;
+}
+
+// Interior unknown q of a level with n nodes per side <-> node (z, y, x), lexicographic.
+__device__ __forceinline__ void unknown_to_node(int dim, int n, int q, int& z, int& y, int& x)
+{
+  const int m1 = n - 2;
+  x = 1 + q % m1;
+  y = 1 + (q / m1) % m1;
+  z = dim == 3 ? 1 + q / (m1 * m1) : 0;
+}
+
+// Coarsest solve by one workgroup: b (shared, >= m doubles) = interior of f in double,
+// u_q = sum_c ainv[c][q] b_c (ainv symmetric: column access keeps a wavefront's reads
+// contiguous).  Ends with the workgroup synchronised.
+template <typename T>
+__device__ __forceinline__ void coarsest_apply(int dim, int n, const double* __restrict__ ainv,
+                                               const T* __restrict__ f, T* __restrict__ u,
+                                               double* b)
+{
+  const int m1 = n - 2;
+  const int m = dim == 3 ? m1 * m1 * m1 : m1 * m1;
+  for (int q = threadIdx.x; q < m; q += blockDim.x) {
+    int z, y, x;
+    unknown_to_node(dim, n, q, z, y, x);
+    b[q] = (double)f[((size_t)z * n + y) * (size_t)n + x];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < m; q += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < m; ++c) s += ainv[(size_t)c * m + q] * b[c];
+    int z, y, x;
+    unknown_to_node(dim, n, q, z, y, x);
+    u[((size_t)z * n + y) * (size_t)n + x] = (T)s;
+  }
+  __syncthreads();
+}
+
 }  // namespace mgk

@@ -198,10 +198,10 @@ class Multigrid:
                                             ctypes.byref(out)))
         return out.value
 
-    def set_fused_smoother(self, fused: bool):
-        """True: temporally blocked smoother on large 3D levels (default); False: per-colour
-        kernel everywhere (bitwise-identical results)."""
-        self._check(lib().mg_set_fused_smoother(self.ctx, int(bool(fused))))
+    def set_fusion(self, enable: bool):
+        """True (default): temporally blocked smoother on large 3D levels and the one-launch
+        coarse tail; False: per-colour smoother and one launch per step (diagnostics)."""
+        self._check(lib().mg_set_fusion(self.ctx, int(bool(enable))))
 
     def close(self):
         if self._ctx is not None:

@@ -84,11 +84,33 @@ def test_blocked_smoother_bitwise_equals_per_colour(n, var):
     out = []
     for fused in (True, False):
         mg = Multigrid(3, n, 6 if n == 161 else 7, variable=var, device=DEV)
-        mg.set_fused_smoother(fused)
+        mg.set_fusion(fused)
         if var:
             mg.set_coefficients(dev(k))
         u = dev(u0)
         mg.smooth(0, f, u, 4)
+        out.append(host(u))
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("dim,n,levels,var,prec", [(2, 129, 6, False, "f64"), (3, 129, 7, False, "f64"),
+                                                    (3, 129, 7, True, "f64"), (3, 65, 6, False, "f32_ir"),
+                                                    (3, 65, 5, True, "f32_ir"), (2, 65, 5, True, "f64")])
+def test_coarse_tail_bitwise_equals_per_level_launches(dim, n, levels, var, prec):
+    """The one-launch coarse tail reproduces the per-level launches bit for bit (levels up to
+    129^3 use no streaming kernels, so the whole cycle must agree exactly)."""
+    say(f"coarse tail dim={dim} n={n} var={var} prec={prec}")
+    k = random_k(dim, n, 24) if var else None
+    f = dev(inputs.uniform_interior(dim, n, 25))
+    out = []
+    for fused in (True, False):
+        mg = Multigrid(dim, n, levels, variable=var, precision=prec, device=DEV)
+        mg.set_fusion(fused)
+        if var:
+            mg.set_coefficients(dev(k))
+        u = mg.zeros()
+        for _ in range(3):
+            mg.vcycle(f, u)
         out.append(host(u))
     assert np.array_equal(out[0], out[1])
 
