@@ -117,34 +117,42 @@ struct Stream {
 
     T U[3][RPW][2], F[3][RPW][2], K[3][RPW][2];
     T PU[RPW][2], PF[RPW][2], PK[RPW][2];
+    float PE[RPW][2];
+    // Loads only issue; the values they bring are first used when the plane enters the
+    // queue one step later (shift_in), so that the residual of the current plane is
+    // computed while they are in flight.
     auto load = [&](int z) {
       const size_t zc = (size_t)min(max(z, 0), n - 1);
-      const bool zin = z >= 1 && z <= n - 2;
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
         const size_t r = zc * n2 + rowoff[i];
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          T v = a.u[r + cx[o]];
-          if (MODE == kNorm) {
-            if (a.zero_interior && zin && rowin[i] && colin[o]) v = T(0);
-          }
-          if (MODE == kRefine) {
-            // e == nullptr: no correction to apply (the first pass of a solve)
-            if (a.e != nullptr && zin && rowin[i] && colin[o]) v = v + (T)a.scale * (T)a.e[r + cx[o]];
-          }
-          PU[i][o] = v;
+          PU[i][o] = a.u[r + cx[o]];
           PF[i][o] = a.f[r + cx[o]];
           if (VAR) PK[i][o] = a.k[r + cx[o]];
+          // e == nullptr: no correction to apply (the first pass of a solve)
+          if (MODE == kRefine && a.e != nullptr) PE[i][o] = a.e[r + cx[o]];
         }
       }
     };
-    auto shift_in = [&]() {
+    // Plane z enters the queue: norm with zero_interior reads the interior of u as 0; the
+    // refinement pass applies u + s e on interior nodes.
+    auto shift_in = [&](int z) {
+      const bool zin = z >= 1 && z <= n - 2;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          U[0][i][o] = U[1][i][o]; U[1][i][o] = U[2][i][o]; U[2][i][o] = PU[i][o];
+          T v = PU[i][o];
+          const bool in = zin && rowin[i] && colin[o];
+          if (MODE == kNorm) {
+            if (a.zero_interior && in) v = T(0);
+          }
+          if (MODE == kRefine) {
+            if (a.e != nullptr && in) v = v + (T)a.scale * (T)PE[i][o];
+          }
+          U[0][i][o] = U[1][i][o]; U[1][i][o] = U[2][i][o]; U[2][i][o] = v;
           F[0][i][o] = F[1][i][o]; F[1][i][o] = F[2][i][o]; F[2][i][o] = PF[i][o];
           if (VAR) { K[0][i][o] = K[1][i][o]; K[1][i][o] = K[2][i][o]; K[2][i][o] = PK[i][o]; }
         }
@@ -163,11 +171,11 @@ struct Stream {
 
     // prologue: planes sbeg-1, sbeg, sbeg+1 in the queue, edges of plane sbeg written
     load(sbeg - 1);
-    shift_in();
+    shift_in(sbeg - 1);
     load(sbeg);
-    shift_in();
+    shift_in(sbeg);
     load(sbeg + 1);
-    shift_in();
+    shift_in(sbeg + 1);
     write_edges(1, 1);  // edges of plane sbeg, read at the first step from buffer 1
 
     T rxprev[RPW];
@@ -178,10 +186,30 @@ struct Stream {
     for (int i = 0; i < RPW / 2; ++i) acc[i] = T(0);
     double sumsq = 0.0;
 
+    // Refinement pass: the results of plane sp are stored one step later (u_out from queue
+    // slot 0, r32 kept in RK), just before the next loads, so that the stores complete in
+    // the shadow of those loads instead of delaying the wait for them.
+    float RK[RPW][2];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) RK[i][0] = RK[i][1] = 0.0f;
+    auto store_refined = [&](int sp) {
+      const size_t zo = (size_t)sp * n2;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          if (!(rowown[i] && colown[o])) continue;
+          const size_t idx = zo + rowoff[i] + cx[o];
+          a.out[idx] = U[0][i][o];
+          a.r32[idx] = RK[i][o];
+        }
+    };
+
     const int last = MODE == kRestrict ? send + 1 : send;
     for (int s = sbeg, step = 0; s <= last; ++s, ++step) {
       const int rb = (step + 1) & 1, wb = step & 1;
       __syncthreads();
+      if (MODE == kRefine && s > sbeg) store_refined(s - 1);
       if (s + 2 <= send + 1) load(s + 2);
 
       if (MODE == kRestrict && s > sbeg) {
@@ -262,7 +290,6 @@ struct Stream {
           }
           sh.erx[wb][w][lane] = rxprev[RPW - 1];
         } else {
-          const size_t zo = (size_t)s * n2;
 #pragma unroll
           for (int i = 0; i < RPW; ++i)
 #pragma unroll
@@ -270,18 +297,16 @@ struct Stream {
               if (!(zin && rowown[i] && colown[o])) continue;
               const double rv = (double)r[i][o];
               sumsq += rv * rv;
-              if (MODE == kRefine) {
-                const size_t idx = zo + rowoff[i] + cx[o];
-                a.out[idx] = U[1][i][o];
-                a.r32[idx] = (float)(rv * a.inv_scale);
-              }
+              if (MODE == kRefine) RK[i][o] = (float)(rv * a.inv_scale);
             }
         }
       }
       // next step: planes s, s+1, s+2; edges of plane s+1 (slot 2 before the shift)
       write_edges(wb, 2);
-      shift_in();
+      shift_in(s + 2);
     }
+    // the last plane (now in queue slot 0)
+    if (MODE == kRefine) store_refined(send);
 
     if (MODE != kRestrict) {
 #pragma unroll

@@ -16,11 +16,15 @@
 //    plane p = zl-1-j when plane zl has just been loaded: plane p's stage j needs planes
 //    p-1 and p+1 after stage j-1, and stage j-1 reached p+1 earlier in the same step and
 //    p-1 one step earlier.  Plane zl-H, H = 2S, is final and is stored.
-//  - Stage j is applied only to nodes at least j+1 positions inside the loaded tile (and
-//    the z-chunk's loaded range): its neighbours then have completed stage j-1.  After 2S
+//  - Stage j is exact on the nodes at least j+1 positions inside the loaded tile (and the
+//    z-chunk's loaded range): their neighbours have completed stage j-1 exactly.  After 2S
 //    stages the final nodes are those at least H = 2S positions inside: the loaded tile
 //    overlaps its neighbours by 2H columns / rows / planes (redundant halo), so tiles are
-//    independent and the result does not depend on the schedule.
+//    independent and the result does not depend on the schedule.  Nodes nearer the edge
+//    are updated too, from incomplete neighbours: such values are read only by other
+//    nodes nearer the edge at later stages and are never stored, so every stage runs on
+//    the whole tile without region tests.  Only nodes of the grid boundary (Dirichlet
+//    values, read by interior neighbours) keep their values.
 //  - Values live in registers: per lane a queue of H+2 planes (z-neighbours are own
 //    registers), x-neighbours come from the adjacent lane by a cross-lane shuffle,
 //    y-neighbours are own registers except across wave boundaries, where the first and
@@ -28,6 +32,7 @@
 //    double-buffered by step parity so that one barrier per plane suffices).
 //  - blockIdx -> tile is XCD-aware: a workgroup b runs on XCD b mod 8, so every XCD is given
 //    a contiguous range of tiles, whose shared halo columns and rows then meet in the same L2.
+#include "mg_buffer.h"
 #include "mg_kernels.h"
 #include "mg_lanes.h"
 #include "mg_stencil.h"
@@ -80,35 +85,38 @@ struct Tiled {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gxa = ox - H + 2 * lane;  // global x of this lane's first column
     const int gyw = oy - H + w * RPW;   // global y of this wave's first row
+    const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;  // adjacent waves
 
-    // Loads use a wave-uniform row pointer plus a per-lane column; coordinates outside the
-    // grid are clamped onto it, so every load is in bounds.  Such positions are never
-    // updated and never read by an updated node (which is interior).
-    int cx[2];
-    unsigned colbits[2];  // bit j: column is interior and inside stage j's region
+    // Addresses: a wave-uniform plane + row base (scalar registers) plus a per-lane 32-bit
+    // column byte offset.  Coordinates outside the grid are clamped onto it, so every load
+    // is in bounds; such positions are never updated and never read by an exact value.
+    // Bit 2i+o of `upd` (per lane): node (row i, column o) is interior to the grid and
+    // may be updated.  Stores go to output rows (`rowout`, uniform) at the column offset
+    // `sxb`, which is out of the plane's range -- the store is dropped -- for columns that
+    // are not output columns of this tile.
+    uint32_t cxb[2], sxb[2];
+    unsigned upd = 0, rowout = 0;
+    uint32_t rowb[RPW];  // clamped row start within a plane, in bytes (uniform)
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
       const int gx = gxa + o, px = 2 * lane + o;
-      cx[o] = min(max(gx, 0), n - 1);
-      const bool in = gx >= 1 && gx <= n - 2;
-      unsigned b = 0;
+      const bool cin = gx >= 1 && gx <= n - 2;
+      const bool cout = cin && px >= H && px <= BX - 1 - H;
+      cxb[o] = (uint32_t)min(max(gx, 0), n - 1) * (uint32_t)sizeof(T);
+      sxb[o] = cout ? cxb[o] : 0x80000000u;
 #pragma unroll
-      for (int j = 0; j < H; ++j) b |= (in && px >= j + 1 && px <= BX - 2 - j) ? (1u << j) : 0u;
-      colbits[o] = b;
+      for (int i = 0; i < RPW; ++i) {
+        const int gy = gyw + i;
+        upd |= (cin && gy >= 1 && gy <= n - 2) ? 1u << (2 * i + o) : 0u;
+      }
     }
-    unsigned rowbits[RPW];  // bit j: row is interior and inside stage j's region (uniform)
-    size_t rowoff[RPW];     // clamped row start within a plane (uniform)
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int gy = gyw + i, pr = w * RPW + i;
-      const bool in = gy >= 1 && gy <= n - 2;
-      unsigned b = 0;
-#pragma unroll
-      for (int j = 0; j < H; ++j) b |= (in && pr >= j + 1 && pr <= BY - 2 - j) ? (1u << j) : 0u;
-      rowbits[i] = b;
-      rowoff[i] = (size_t)min(max(gy, 0), n - 1) * (size_t)n;
+      rowout |= (gy >= 1 && gy <= n - 2 && pr >= H && pr <= BY - 1 - H) ? 1u << i : 0u;
+      rowb[i] = (uint32_t)(min(max(gy, 0), n - 1) * n) * (uint32_t)sizeof(T);
     }
-    const size_t n2 = (size_t)n * (size_t)n;
+    const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * sizeof(T));
 
     T U[Q][RPW][2], F[Q][RPW][2], K[Q][RPW][2];
     T PU[RPW][2], PF[RPW][2], PK[RPW][2];
@@ -165,17 +173,16 @@ struct Tiled {
             for (int c = 0; c < 2; ++c) EA[r][c] = EB[r][c];
         }
       }
+      const size_t zb = zc * planeb;
+      const PlaneBuf bu = plane_buf(uin, zb, planeb), bf = plane_buf(f, zb, planeb);
+      const PlaneBuf bk = plane_buf(VAR ? k : f, zb, planeb);
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        const size_t r = zc * n2 + rowoff[i];
-        const T* up = uin + r;
-        const T* fp = f + r;
-        const T* kp = VAR ? k + r : nullptr;
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          PU[i][o] = IN == kInZero ? T(0) : up[cx[o]];
-          PF[i][o] = fp[cx[o]];
-          if (VAR) PK[i][o] = kp[cx[o]];
+          PU[i][o] = IN == kInZero ? T(0) : buf_load<T>(bu, cxb[o], rowb[i]);
+          PF[i][o] = buf_load<T>(bf, cxb[o], rowb[i]);
+          if (VAR) PK[i][o] = buf_load<T>(bk, cxb[o], rowb[i]);
         }
       }
     };
@@ -212,8 +219,7 @@ struct Tiled {
                 for (int c2 = 0; c2 < mx; ++c2)
                   sum = sum + (wz * wy * wx) * (a2 == 0 ? EA[rb + b2][cb + c2] : EB[rb + b2][cb + c2]);
             }
-            const bool in = zin && gyw + i >= 1 && gyw + i <= n - 2 && gxa + o >= 1 &&
-                            gxa + o <= n - 2;
+            const bool in = zin && ((upd >> (2 * i + o)) & 1u);
             if (in) v = v + sum;
           }
           U[s0][i][o] = v;
@@ -222,13 +228,18 @@ struct Tiled {
         }
     };
 
-    // stage j updates plane p only for p in [plo_j, phi_j]
-    int plo[H], phi[H];
+    // final plane pout (queue slot SO) -> uout, if it belongs to this z-chunk
+    auto store = [&](int pout, auto SOC) {
+      constexpr int so = decltype(SOC)::value;
+      if (pout < z0 || pout >= z1) return;
+      const PlaneBuf bo = plane_buf(uout, (size_t)pout * planeb, planeb);
 #pragma unroll
-    for (int j = 0; j < H; ++j) {
-      plo[j] = max(1, z0 - (H - 1 - j));
-      phi[j] = min(n - 2, z1 - 1 + (H - 1 - j));
-    }
+      for (int i = 0; i < RPW; ++i) {
+        if (!((rowout >> i) & 1u)) continue;
+#pragma unroll
+        for (int o = 0; o < 2; ++o) buf_store(U[so][i][o], bo, sxb[o], rowb[i]);
+      }
+    };
 
     const int zbeg = z0 - H, zend = z1 + H;  // planes loaded: [zbeg, zend)
     int zl = zbeg;
@@ -245,6 +256,10 @@ struct Tiled {
       // the prefetched plane zl enters the queue
       insert(zl, IC<s0>{});
       __syncthreads();
+      // Plane zl-1-H became final in the previous step and is still queued (slot
+      // P-H-1): storing it here, just before the next loads, lets the stores complete in
+      // the shadow of the loads instead of delaying the next step's wait for them.
+      store(zl - 1 - H, IC<imod(P - H - 1, Q)>{});
       if (zl + 1 < zend) load(zl + 1);
       const int rb = (step + 1) & 1;  // LDS buffer written in the previous step
       const int wb = step & 1;        // LDS buffer written in this step
@@ -252,14 +267,13 @@ struct Tiled {
 #pragma unroll
       for (int j = 0; j < H; ++j) {
         const int p = zl - 1 - j;
-        if (p < plo[j] || p > phi[j]) continue;  // uniform across the workgroup
+        if (p < 1 || p > n - 2) continue;  // boundary planes keep their values (uniform)
         const int cs = imod(P - 1 - j, Q);  // centre plane p
         const int cm = imod(P - 2 - j, Q);  // plane p - 1
         const int cp = imod(P - j, Q);      // plane p + 1
         const int pslot = imod(p, H);
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
-          if (!((rowbits[i] >> j) & 1u)) continue;  // uniform across the wave
           const int o = (B0 + i + P) & 1;
           // x-neighbours: own other column, or the neighbouring lane's
           T xm, xp, kxm = T(0), kxp = T(0);
@@ -272,21 +286,22 @@ struct Tiled {
             xp = from_lane_above(U[cs][i][0]);
             if (VAR) { kxm = K[cs][i][0]; kxp = from_lane_above(K[cs][i][0]); }
           }
-          // y-neighbours in column o: own rows, or the adjacent wave's edge row
-          T ym = T(0), yp = T(0), kym = T(0), kyp = T(0);
+          // y-neighbours in column o: own rows, or the adjacent wave's edge row (the first
+          // and the last wave read their own rows there: tile-edge values, never exact)
+          T ym, yp, kym = T(0), kyp = T(0);
           if (i > 0) {
             ym = U[cs][i - 1][o];
             if (VAR) kym = K[cs][i - 1][o];
-          } else if (w > 0) {
-            ym = sh.eu[rb][pslot][w - 1][1][lane];
-            if (VAR) kym = sh.ek[rb][pslot][w - 1][1][lane];
+          } else {
+            ym = sh.eu[rb][pslot][wm][1][lane];
+            if (VAR) kym = sh.ek[rb][pslot][wm][1][lane];
           }
           if (i < RPW - 1) {
             yp = U[cs][i + 1][o];
             if (VAR) kyp = K[cs][i + 1][o];
-          } else if (w < W - 1) {
-            yp = sh.eu[rb][pslot][w + 1][0][lane];
-            if (VAR) kyp = sh.ek[rb][pslot][w + 1][0][lane];
+          } else {
+            yp = sh.eu[rb][pslot][wp][0][lane];
+            if (VAR) kyp = sh.ek[rb][pslot][wp][0][lane];
           }
           const T zm = U[cm][i][o], zp = U[cp][i][o];
           const T h2f = h2 * F[cs][i][o];
@@ -297,7 +312,7 @@ struct Tiled {
             v = gs_var<T, 3>(h2f, K[cs][i][o], xm, kxm, xp, kxp, ym, kym, yp, kyp, zm,
                              K[cm][i][o], zp, K[cp][i][o]);
           }
-          const bool act = (colbits[o] >> j) & 1u;
+          const bool act = (upd >> (2 * i + o)) & 1u;
           U[cs][i][o] = act ? v : U[cs][i][o];
         }
       }
@@ -323,19 +338,8 @@ struct Tiled {
         }
       }
 
-      // store the finished plane zl - H
-      const int pout = zl - H;
-      if (pout >= z0 && pout < z1) {
-        constexpr int so = imod(P - H, Q);
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-          if (!((rowbits[i] >> (H - 1)) & 1u)) continue;
-          T* op = uout + (size_t)pout * n2 + rowoff[i];
-#pragma unroll
-          for (int o = 0; o < 2; ++o)
-            if ((colbits[o] >> (H - 1)) & 1u) op[cx[o]] = U[so][i][o];
-        }
-      }
+      // the last step stores its own finished plane zl - H
+      if (zl + 1 == zend) store(zl - H, IC<imod(P - H, Q)>{});
       ++step;
       ++zl;
       return zl < zend;
