@@ -150,12 +150,26 @@ mg_status mg_coarsest_solve(mg_ctx* ctx, const double* f, double* u);
  * fixed order (bitwise reproducible).  Synchronises the stream. */
 mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, double* norm2);
 
-/* Kernel-fusion switch (diagnostics and tests).  enable = 1 (default): the temporally
- * blocked out-of-place smoother on large 3D levels and the one-launch coarse tail of the
- * V-cycle (all levels with at most 4096 interior nodes); enable = 0: the per-colour
- * smoother and one launch per step everywhere.  Smoothing results are bitwise identical
- * either way, and so is the coarse tail. */
-mg_status mg_set_fusion(mg_ctx* ctx, int enable);
+/* Kernel-fusion flags (diagnostics and tests), a bitwise OR of:
+ *  MG_FUSE_BLOCKED  temporally blocked out-of-place smoother and single-pass streaming
+ *                   residual / restriction / norm / refinement kernels on large 3D levels
+ *                   (otherwise the per-colour smoother and one launch per step);
+ *  MG_FUSE_PROLONG  on such levels, the coarse-grid correction u += P e applied inside the
+ *                   first post-smoothing pass (FP32 passes) instead of a separate pass;
+ *  MG_FUSE_ZERO     a zero initial guess read as 0 by the first pre-smoothing pass instead
+ *                   of being written first;
+ *  MG_FUSE_TAIL     all levels with at most 4096 interior nodes in one launch.
+ * Default MG_FUSE_ALL.  Clearing MG_FUSE_PROLONG, MG_FUSE_ZERO or MG_FUSE_TAIL leaves every
+ * result bitwise unchanged; without MG_FUSE_BLOCKED smoothing results are unchanged but
+ * residual sums are accumulated in another order.  EINVAL for bits outside MG_FUSE_ALL. */
+enum {
+  MG_FUSE_BLOCKED = 1,
+  MG_FUSE_PROLONG = 2,
+  MG_FUSE_ZERO = 4,
+  MG_FUSE_TAIL = 8,
+  MG_FUSE_ALL = 15
+};
+mg_status mg_set_fusion(mg_ctx* ctx, int flags);
 
 /* Message for the last failing call on ctx, or for the last failing mg_setup /
  * mg_validate call of this thread when ctx is NULL.  Never NULL. */

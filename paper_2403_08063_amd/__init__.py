@@ -11,6 +11,8 @@ iterative-refinement form and a differentiable variable-coefficient form.
 """
 from .solver import Multigrid, SolveInfo, default_levels  # noqa: F401
 from .autograd import MGSolve, solve  # noqa: F401
-from ._lib import MgError  # noqa: F401
+from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_TAIL, FUSE_ZERO,  # noqa: F401
+                   MgError)
 
-__all__ = ["Multigrid", "SolveInfo", "MGSolve", "solve", "MgError", "default_levels"]
+__all__ = ["Multigrid", "SolveInfo", "MGSolve", "solve", "MgError", "default_levels",
+           "FUSE_ALL", "FUSE_BLOCKED", "FUSE_PROLONG", "FUSE_TAIL", "FUSE_ZERO"]

@@ -15,6 +15,9 @@ MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_ENOCONV, MG_ENAN, MG_ESTATE = range(7)
 STATUS_NAMES = {0: "MG_OK", 1: "MG_EINVAL", 2: "MG_ENOMEM", 3: "MG_EHIP", 4: "MG_ENOCONV",
                 5: "MG_ENAN", 6: "MG_ESTATE"}
 MG_F64, MG_F32_IR = 0, 1
+# kernel-fusion flags (mg_set_fusion)
+FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL = 1, 2, 4, 8
+FUSE_ALL = 15
 
 # every function declared in include/mg.h
 EXPORTS = [

@@ -47,7 +47,7 @@ struct mg_ctx {
   double* partial = nullptr;
   double* scal = nullptr;  // device scalars: [0] norm2, [1] rhs norm2
   bool coeffs = false;
-  bool fused = true;
+  int fuse = MG_FUSE_ALL;  // kernel-fusion flags (mg_set_fusion)
   int tail_first = -1;  // first level handled by the one-launch coarse tail (-1: none)
   char err[512] = "no error";
 };
@@ -183,7 +183,7 @@ View<float> view<float>(mg_ctx* c, int l)
 
 bool use_tiled(const mg_ctx* c, int l)
 {
-  return c->fused && mgk::rbgs_tiled_supported(c->g.dim, c->lv[l].n);
+  return (c->fuse & MG_FUSE_BLOCKED) && mgk::rbgs_tiled_supported(c->g.dim, c->lv[l].n);
 }
 
 // `sweeps` red-black sweeps on level l.  u holds the iterate, t is the level's second
@@ -196,7 +196,8 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
 {
   const Level& L = c->lv[l];
   const int dim = c->g.dim;
-  if (ec && (sweeps == 0 || !use_tiled(c, l) || !mgk::rbgs_tiled_fuses_prolong(sizeof(T)))) {
+  if (ec && (sweeps == 0 || !use_tiled(c, l) || !(c->fuse & MG_FUSE_PROLONG) ||
+             !mgk::rbgs_tiled_fuses_prolong(sizeof(T)))) {
     // coarse-grid correction as a separate pass when it cannot ride on a fused sweep
     mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, u);
     ec = nullptr;
@@ -206,6 +207,10 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
     return u;
   }
   if (use_tiled(c, l)) {
+    if (zero_guess && !(c->fuse & MG_FUSE_ZERO)) {
+      mgk::fill<T>(c->s, L.N, T(0), u);
+      zero_guess = false;
+    }
     T* cur = u;
     T* other = t;
     int left = sweeps;
@@ -239,7 +244,7 @@ T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
   const int dim = c->g.dim;
   const Level& L = c->lv[l];
   const View<T> V = view<T>(c, l);
-  if (c->fused && l == c->tail_first && zero_guess && u == V.u && f == V.f) {
+  if ((c->fuse & MG_FUSE_TAIL) && l == c->tail_first && zero_guess && u == V.u && f == V.f) {
     // levels l .. coarsest in one launch (same arithmetic as the per-level kernels)
     mgk::TailArgs<T> a{};
     a.nlev = c->g.levels - l;
@@ -630,10 +635,11 @@ mg_status mg_residual_norm2(mg_ctx* c, const double* f, const double* u, double*
   return read_scalar(c, c->scal, out);
 }
 
-mg_status mg_set_fusion(mg_ctx* c, int enable)
+mg_status mg_set_fusion(mg_ctx* c, int flags)
 {
   if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
-  c->fused = enable != 0;
+  if (flags & ~MG_FUSE_ALL) return fail(c, MG_EINVAL, "unknown fusion flags 0x%x", flags);
+  c->fuse = flags;
   return MG_OK;
 }
 

@@ -22,17 +22,24 @@
 // 2Y and FW_y combines rows 2Y-1, 2Y, 2Y+1 one step later (the row above a wave comes from
 // the previous wave through LDS); FW_z accumulates over the fine planes 2Z-1, 2Z, 2Z+1.
 // Paper: the residual-norm stopping test of Sect. 5; the operators of Sect. 5, Eq. 1.
+#include "mg_buffer.h"
 #include "mg_kernels.h"
 #include "mg_lanes.h"
 #include "mg_stencil.h"
 
+#include <type_traits>
+
 namespace mgk {
 namespace {
 
+template <int V>
+using IC = std::integral_constant<int, V>;
+
 enum { kRestrict = 0, kNorm = 1, kRefine = 2 };
 
-template <typename T, bool VAR, int MODE, int W, int RPW>
+template <typename T, bool VAR, int MODE, int W, int RPW, int PD>
 struct Stream {
+  static_assert(PD == 1 || PD == 2, "prefetch depth");
   static constexpr int BX = 128;
   static constexpr int BY = W * RPW;
   // restriction: coarse columns / rows per tile; norm, refinement: fine output per tile
@@ -42,8 +49,9 @@ struct Stream {
 
   struct Shared {
     T eu[2][W][2][2][64];  // edge rows of u: [buffer][wave][first/last row][column][lane]
-    T ek[VAR ? 2 : 1][W][2][2][64];
-    T erx[2][W][64];       // restriction: x-filtered residual of a wave's last row
+    T ek[VAR ? 2 : 1][VAR ? W : 1][2][2][64];
+    // restriction: x-filtered residual of a wave's last row
+    T erx[2][MODE == kRestrict ? W : 1][64];
     double red[W];
   };
 
@@ -95,66 +103,97 @@ struct Stream {
     const int gxa = gx0 + 2 * lane;
     const int gyw = gy0 + w * RPW;
 
-    int cx[2];
+    // Addresses: per-plane buffer resources, a uniform row byte offset and a per-lane
+    // column byte offset (for arrays of T and, in the refinement pass, of float).  Clamped
+    // coordinates keep every load in bounds.  Store offsets of columns this tile does not
+    // own are out of the plane's range, so those stores are dropped.
+    uint32_t cxb[2], sxb[2], cxf[2], sxf[2];
     bool colin[2], colown[2];
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
       const int gx = gxa + o, px = 2 * lane + o;
-      cx[o] = min(max(gx, 0), n - 1);
+      const uint32_t c = (uint32_t)min(max(gx, 0), n - 1);
       colin[o] = gx >= 1 && gx <= n - 2;
       colown[o] = colin[o] && px >= 1 && px <= BX - 2;
+      cxb[o] = c * (uint32_t)sizeof(T);
+      sxb[o] = colown[o] ? cxb[o] : 0x80000000u;
+      cxf[o] = c * 4u;
+      sxf[o] = colown[o] ? cxf[o] : 0x80000000u;
     }
-    size_t rowoff[RPW];
+    uint32_t rowb[RPW], rowf[RPW];
     bool rowin[RPW], rowown[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int gy = gyw + i, pr = w * RPW + i;
-      rowoff[i] = (size_t)min(max(gy, 0), n - 1) * (size_t)n;
+      const uint32_t r = (uint32_t)(min(max(gy, 0), n - 1) * n);
+      rowb[i] = r * (uint32_t)sizeof(T);
+      rowf[i] = r * 4u;
       rowin[i] = gy >= 1 && gy <= n - 2;
       rowown[i] = rowin[i] && pr >= 1 && pr <= BY - 2;
     }
-    const size_t n2 = (size_t)n * (size_t)n;
+    const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * sizeof(T));
+    const uint32_t planef = (uint32_t)((size_t)n * (size_t)n * 4u);
+    const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;  // adjacent waves
 
+    // Queue of the planes s-1, s, s+1 and PD prefetch buffers.  PD = 2: at step s the
+    // loads of plane s+3 are issued into one buffer while plane s+2 (issued a step earlier)
+    // waits in the other, so each load has two steps' work to arrive in.  PD = 1 (fewer
+    // registers): plane s+2 is loaded and consumed in step s.
     T U[3][RPW][2], F[3][RPW][2], K[3][RPW][2];
-    T PU[RPW][2], PF[RPW][2], PK[RPW][2];
-    float PE[RPW][2];
-    // Loads only issue; the values they bring are first used when the plane enters the
-    // queue one step later (shift_in), so that the residual of the current plane is
-    // computed while they are in flight.
-    auto load = [&](int z) {
+    T PU[PD][RPW][2], PF[PD][RPW][2], PK[PD][RPW][2];
+    float PE[PD][RPW][2];
+    auto load = [&](auto BC, int z) {
+      constexpr int bb = decltype(BC)::value;
       const size_t zc = (size_t)min(max(z, 0), n - 1);
+      const PlaneBuf bu = plane_buf(a.u, zc * planeb, planeb);
+      const PlaneBuf bf = plane_buf(a.f, zc * planeb, planeb);
 #pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        const size_t r = zc * n2 + rowoff[i];
+      for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          PU[i][o] = a.u[r + cx[o]];
-          PF[i][o] = a.f[r + cx[o]];
-          if (VAR) PK[i][o] = a.k[r + cx[o]];
-          // e == nullptr: no correction to apply (the first pass of a solve)
-          if (MODE == kRefine && a.e != nullptr) PE[i][o] = a.e[r + cx[o]];
+          PU[bb][i][o] = buf_load<T>(bu, cxb[o], rowb[i]);
+          PF[bb][i][o] = buf_load<T>(bf, cxb[o], rowb[i]);
+        }
+      if constexpr (VAR) {
+        const PlaneBuf bk = plane_buf(a.k, zc * planeb, planeb);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+          for (int o = 0; o < 2; ++o) PK[bb][i][o] = buf_load<T>(bk, cxb[o], rowb[i]);
+      }
+      // e == nullptr: no correction to apply (the first pass of a solve)
+      if constexpr (MODE == kRefine) {
+        if (a.e != nullptr) {
+          const PlaneBuf be = plane_buf(a.e, zc * planef, planef);
+#pragma unroll
+          for (int i = 0; i < RPW; ++i)
+#pragma unroll
+            for (int o = 0; o < 2; ++o) PE[bb][i][o] = buf_load<float>(be, cxf[o], rowf[i]);
         }
       }
     };
-    // Plane z enters the queue: norm with zero_interior reads the interior of u as 0; the
-    // refinement pass applies u + s e on interior nodes.
-    auto shift_in = [&](int z) {
+    // Plane z enters the queue from buffer BB: norm with zero_interior reads the interior
+    // of u as 0; the refinement pass applies u + s e on interior nodes.
+    auto shift_in = [&](auto BC, int z) {
+      constexpr int bb = decltype(BC)::value;
       const bool zin = z >= 1 && z <= n - 2;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          T v = PU[i][o];
+          T v = PU[bb][i][o];
           const bool in = zin && rowin[i] && colin[o];
-          if (MODE == kNorm) {
+          if constexpr (MODE == kNorm) {
             if (a.zero_interior && in) v = T(0);
           }
-          if (MODE == kRefine) {
-            if (a.e != nullptr && in) v = v + (T)a.scale * (T)PE[i][o];
+          if constexpr (MODE == kRefine) {
+            if (a.e != nullptr && in) v = v + (T)a.scale * (T)PE[bb][i][o];
           }
           U[0][i][o] = U[1][i][o]; U[1][i][o] = U[2][i][o]; U[2][i][o] = v;
-          F[0][i][o] = F[1][i][o]; F[1][i][o] = F[2][i][o]; F[2][i][o] = PF[i][o];
-          if (VAR) { K[0][i][o] = K[1][i][o]; K[1][i][o] = K[2][i][o]; K[2][i][o] = PK[i][o]; }
+          F[0][i][o] = F[1][i][o]; F[1][i][o] = F[2][i][o]; F[2][i][o] = PF[bb][i][o];
+          if constexpr (VAR) {
+            K[0][i][o] = K[1][i][o]; K[1][i][o] = K[2][i][o]; K[2][i][o] = PK[bb][i][o];
+          }
         }
     };
     auto write_edges = [&](int buf, int slot) {  // first and last row of a queued plane
@@ -162,21 +201,24 @@ struct Stream {
       for (int o = 0; o < 2; ++o) {
         sh.eu[buf][w][0][o][lane] = U[slot][0][o];
         sh.eu[buf][w][1][o][lane] = U[slot][RPW - 1][o];
-        if (VAR) {
+        if constexpr (VAR) {
           sh.ek[buf][w][0][o][lane] = K[slot][0][o];
           sh.ek[buf][w][1][o][lane] = K[slot][RPW - 1][o];
         }
       }
     };
 
-    // prologue: planes sbeg-1, sbeg, sbeg+1 in the queue, edges of plane sbeg written
-    load(sbeg - 1);
-    shift_in(sbeg - 1);
-    load(sbeg);
-    shift_in(sbeg);
-    load(sbeg + 1);
-    shift_in(sbeg + 1);
+    // prologue: planes sbeg-1, sbeg, sbeg+1 in the queue, edges of plane sbeg written,
+    // plane sbeg+2 on its way into buffer 0
+    load(IC<0>{}, sbeg - 1);
+    shift_in(IC<0>{}, sbeg - 1);
+    load(IC<0>{}, sbeg);
+    shift_in(IC<0>{}, sbeg);
+    load(IC<0>{}, sbeg + 1);
+    shift_in(IC<0>{}, sbeg + 1);
     write_edges(1, 1);  // edges of plane sbeg, read at the first step from buffer 1
+    const int lastload = send + 1;  // the last plane any step reads
+    if (PD == 2 && sbeg + 2 <= lastload) load(IC<0>{}, sbeg + 2);
 
     T rxprev[RPW];
     T acc[RPW / 2];
@@ -193,24 +235,29 @@ struct Stream {
 #pragma unroll
     for (int i = 0; i < RPW; ++i) RK[i][0] = RK[i][1] = 0.0f;
     auto store_refined = [&](int sp) {
-      const size_t zo = (size_t)sp * n2;
+      const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
+      const PlaneBuf br = plane_buf(a.r32, (size_t)sp * planef, planef);
 #pragma unroll
-      for (int i = 0; i < RPW; ++i)
+      for (int i = 0; i < RPW; ++i) {
+        if (!rowown[i]) continue;
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          if (!(rowown[i] && colown[o])) continue;
-          const size_t idx = zo + rowoff[i] + cx[o];
-          a.out[idx] = U[0][i][o];
-          a.r32[idx] = RK[i][o];
+          buf_store(U[0][i][o], bo, sxb[o], rowb[i]);
+          buf_store(RK[i][o], br, sxf[o], rowf[i]);
         }
+      }
     };
 
-    const int last = MODE == kRestrict ? send + 1 : send;
-    for (int s = sbeg, step = 0; s <= last; ++s, ++step) {
-      const int rb = (step + 1) & 1, wb = step & 1;
+    // One step at plane s; the step's parity BB (step count from sbeg) selects the
+    // prefetch buffer and the LDS edge buffers.
+    auto stepfn = [&](auto BC, int s) {
+      constexpr int bb = decltype(BC)::value;
+      constexpr int rb = 1 - bb, wb = bb;  // LDS buffer written in the previous / this step
       __syncthreads();
       if (MODE == kRefine && s > sbeg) store_refined(s - 1);
-      if (s + 2 <= send + 1) load(s + 2);
+      constexpr int lb = PD == 2 ? 1 - bb : 0;  // buffer of this step's loads
+      constexpr int cb = PD == 2 ? bb : 0;      // buffer of the plane entering the queue
+      if (s + PD + 1 <= lastload) load(IC<lb>{}, s + PD + 1);
 
       if (MODE == kRestrict && s > sbeg) {
         // FW_y of plane s-1 for the coarse rows at even fine rows, then FW_z over the fine
@@ -246,27 +293,38 @@ struct Stream {
       }
 
       if (s <= send) {
-        // residual at plane s (queue slot 1), every own node
+        // residual at plane s (queue slot 1), every node; the first and the last wave read
+        // their own edge rows at the tile edge, where no residual is used
         T r[RPW][2];
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
           const T l1 = from_lane_below(U[1][i][1]);
           const T r0 = from_lane_above(U[1][i][0]);
           T kl1 = T(0), kr0 = T(0);
-          if (VAR) { kl1 = from_lane_below(K[1][i][1]); kr0 = from_lane_above(K[1][i][0]); }
+          if constexpr (VAR) { kl1 = from_lane_below(K[1][i][1]); kr0 = from_lane_above(K[1][i][0]); }
 #pragma unroll
           for (int o = 0; o < 2; ++o) {
             const T ui = U[1][i][o];
             const T xm = o == 0 ? l1 : U[1][i][0];
             const T xp = o == 0 ? U[1][i][1] : r0;
-            T ym = T(0), yp = T(0), kym = T(0), kyp = T(0);
-            if (i > 0) { ym = U[1][i - 1][o]; if (VAR) kym = K[1][i - 1][o]; }
-            else if (w > 0) { ym = sh.eu[rb][w - 1][1][o][lane]; if (VAR) kym = sh.ek[rb][w - 1][1][o][lane]; }
-            if (i < RPW - 1) { yp = U[1][i + 1][o]; if (VAR) kyp = K[1][i + 1][o]; }
-            else if (w < W - 1) { yp = sh.eu[rb][w + 1][0][o][lane]; if (VAR) kyp = sh.ek[rb][w + 1][0][o][lane]; }
+            T ym, yp, kym = T(0), kyp = T(0);
+            if (i > 0) {
+              ym = U[1][i - 1][o];
+              if constexpr (VAR) kym = K[1][i - 1][o];
+            } else {
+              ym = sh.eu[rb][wm][1][o][lane];
+              if constexpr (VAR) kym = sh.ek[rb][wm][1][o][lane];
+            }
+            if (i < RPW - 1) {
+              yp = U[1][i + 1][o];
+              if constexpr (VAR) kyp = K[1][i + 1][o];
+            } else {
+              yp = sh.eu[rb][wp][0][o][lane];
+              if constexpr (VAR) kyp = sh.ek[rb][wp][0][o][lane];
+            }
             const T zm = U[0][i][o], zp = U[2][i][o];
             T au;
-            if (!VAR) {
+            if constexpr (!VAR) {
               au = au_const<T, 3>(a.ih2, ui, xm, xp, ym, yp, zm, zp);
             } else {
               const T kxm = o == 0 ? kl1 : K[1][i][0];
@@ -278,7 +336,7 @@ struct Stream {
           }
         }
         const bool zin = s >= 1 && s <= n - 2;
-        if (MODE == kRestrict) {
+        if constexpr (MODE == kRestrict) {
           // fine nodes outside the interior carry no residual
 #pragma unroll
           for (int i = 0; i < RPW; ++i) {
@@ -297,13 +355,21 @@ struct Stream {
               if (!(zin && rowown[i] && colown[o])) continue;
               const double rv = (double)r[i][o];
               sumsq += rv * rv;
-              if (MODE == kRefine) RK[i][o] = (float)(rv * a.inv_scale);
+              if constexpr (MODE == kRefine) RK[i][o] = (float)(rv * a.inv_scale);
             }
         }
       }
       // next step: planes s, s+1, s+2; edges of plane s+1 (slot 2 before the shift)
       write_edges(wb, 2);
-      shift_in(s + 2);
+      shift_in(IC<cb>{}, s + 2);
+    };
+
+    const int last = MODE == kRestrict ? send + 1 : send;
+    for (int s = sbeg; s <= last;) {
+      stepfn(IC<0>{}, s);
+      if (++s > last) break;
+      stepfn(IC<1>{}, s);
+      ++s;
     }
     // the last plane (now in queue slot 0)
     if (MODE == kRefine) store_refined(send);
@@ -323,10 +389,10 @@ struct Stream {
   }
 };
 
-template <typename T, bool VAR, int MODE, int W, int RPW>
-__global__ void __launch_bounds__(64 * W) k_stream(typename Stream<T, VAR, MODE, W, RPW>::Args a)
+template <typename T, bool VAR, int MODE, int W, int RPW, int PD>
+__global__ void __launch_bounds__(64 * W) k_stream(typename Stream<T, VAR, MODE, W, RPW, PD>::Args a)
 {
-  using C = Stream<T, VAR, MODE, W, RPW>;
+  using C = Stream<T, VAR, MODE, W, RPW, PD>;
   __shared__ typename C::Shared sh;
   C::run(a, sh);
 }
@@ -385,6 +451,28 @@ constexpr int kW = 8, kRPW = 4;          // restriction
 constexpr int kNW = 8, kNRPW = 2;        // norm
 constexpr int kRW = 16, kRRPW = 2;       // refinement pass
 constexpr int kRVW = 8;                  // ... with variable k (16 waves would spill registers)
+// Prefetch depth: 2 wherever the second buffer keeps the occupancy (the FP64
+// variable-coefficient restriction would spill registers with it).
+#ifndef MG_RESTRICT32_PD
+#define MG_RESTRICT32_PD 2
+#endif
+template <typename T, bool VAR>
+constexpr int restrict_pd()
+{
+  return (sizeof(T) == 4 && !VAR) ? MG_RESTRICT32_PD : (VAR && sizeof(T) == 8) ? 1 : 2;
+}
+// The FP64 variable-coefficient restriction holds k as well: 12 waves of 2 rows keep it
+// within the register file.
+template <typename T, bool VAR>
+constexpr int restrict_w()
+{
+  return (VAR && sizeof(T) == 8) ? 12 : kW;
+}
+template <typename T, bool VAR>
+constexpr int restrict_rpw()
+{
+  return (VAR && sizeof(T) == 8) ? 2 : kRPW;
+}
 
 }  // namespace
 
@@ -394,29 +482,35 @@ void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const 
 {
   const int nc = (nf - 1) / 2 + 1;
   const int m = nc - 2;
-  auto launch = [&](auto kern, auto argsproto) {
+  auto launch = [&](auto kern, auto argsproto, int w, int rpw) {
     using A = decltype(argsproto);
     A a{};
     a.f = f; a.u = u; a.k = k; a.out = fc; a.n = nf; a.ih2 = (T)(1.0 / (h * h));
     a.tiles_x = (m + 61) / 62;
-    constexpr int cy = kW * kRPW / 2 - 2;
+    const int cy = w * rpw / 2 - 2;
     a.tiles_y = (m + cy - 1) / cy;
     const int per = a.tiles_x * a.tiles_y;
-    a.zlen = best_zlen(per, m, 1, capacity_of(kern, 64 * kW), 1 << 30);
+    a.zlen = best_zlen(per, m, 1, capacity_of(kern, 64 * w), 1 << 30);
     const int blocks = per * ((m + a.zlen - 1) / a.zlen);
-    kern<<<blocks, 64 * kW, 0, s>>>(a);
+    kern<<<blocks, 64 * w, 0, s>>>(a);
   };
-  if (k) launch(k_stream<T, true, kRestrict, kW, kRPW>, typename Stream<T, true, kRestrict, kW, kRPW>::Args{});
-  else launch(k_stream<T, false, kRestrict, kW, kRPW>, typename Stream<T, false, kRestrict, kW, kRPW>::Args{});
+  constexpr int pv = restrict_pd<T, true>(), pc = restrict_pd<T, false>();
+  constexpr int wv = restrict_w<T, true>(), rv = restrict_rpw<T, true>();
+  if (k)
+    launch(k_stream<T, true, kRestrict, wv, rv, pv>,
+           typename Stream<T, true, kRestrict, wv, rv, pv>::Args{}, wv, rv);
+  else
+    launch(k_stream<T, false, kRestrict, kW, kRPW, pc>,
+           typename Stream<T, false, kRestrict, kW, kRPW, pc>::Args{}, kW, kRPW);
 }
 
 namespace {
 template <bool VAR, int MODE, int W, int RPW>
-void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, W, RPW>::Args a, double* partial,
+void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, W, RPW, 2>::Args a, double* partial,
                  double* out)
 {
-  using C = Stream<double, VAR, MODE, W, RPW>;
-  auto kern = k_stream<double, VAR, MODE, W, RPW>;
+  using C = Stream<double, VAR, MODE, W, RPW, 2>;
+  auto kern = k_stream<double, VAR, MODE, W, RPW, 2>;
   const int m = a.n - 2;
   a.tiles_x = (m + C::OX - 1) / C::OX;
   a.tiles_y = (m + C::OY - 1) / C::OY;
@@ -433,11 +527,11 @@ void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const do
                        const double* u, int mode, double* partial, double* out)
 {
   if (k) {
-    Stream<double, true, kNorm, kNW, kNRPW>::Args a{};
+    Stream<double, true, kNorm, kNW, kNRPW, 2>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
     launch_fine<true, kNorm, kNW, kNRPW>(s, a, partial, out);
   } else {
-    Stream<double, false, kNorm, kNW, kNRPW>::Args a{};
+    Stream<double, false, kNorm, kNW, kNRPW, 2>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
     launch_fine<false, kNorm, kNW, kNRPW>(s, a, partial, out);
   }
@@ -448,12 +542,12 @@ void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double
                    float* r32, double* partial, double* out)
 {
   if (k) {
-    Stream<double, true, kRefine, kRVW, kRRPW>::Args a{};
+    Stream<double, true, kRefine, kRVW, kRRPW, 2>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
     a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
     launch_fine<true, kRefine, kRVW, kRRPW>(s, a, partial, out);
   } else {
-    Stream<double, false, kRefine, kRW, kRRPW>::Args a{};
+    Stream<double, false, kRefine, kRW, kRRPW, 2>::Args a{};
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
     a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
     launch_fine<false, kRefine, kRW, kRRPW>(s, a, partial, out);

@@ -49,8 +49,9 @@ enum { kInRead = 0, kInZero = 1, kInProlong = 2 };
 
 constexpr int imod(int a, int m) { return ((a % m) + m) % m; }
 
-template <typename T, bool VAR, int S, int W, int RPW>
+template <typename T, bool VAR, int S, int W, int RPW, int PD>
 struct Tiled {
+  static_assert(PD == 1 || PD == 2, "prefetch depth");
   static constexpr int H = 2 * S;        // halo = number of stages
   static constexpr int BX = 128;         // columns per tile (2 per lane)
   static constexpr int BY = W * RPW;     // rows per tile
@@ -119,7 +120,10 @@ struct Tiled {
     const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * sizeof(T));
 
     T U[Q][RPW][2], F[Q][RPW][2], K[Q][RPW][2];
-    T PU[RPW][2], PF[RPW][2], PK[RPW][2];
+    // Prefetch buffers: plane zl+PD is loaded in the step that inserts plane zl, so each
+    // load has PD steps' work to arrive in; with PD = 2 the buffer is chosen by the
+    // plane's parity.
+    T PU[PD][RPW][2], PF[PD][RPW][2], PK[PD][RPW][2];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -132,46 +136,40 @@ struct Tiled {
         }
 
     // Fused prolongation: coarse column cxa = (gxa - 1) / 2 and cxa + 1, coarse rows
-    // cya .. cya + RPW/2 with cya = (gyw - 1) / 2, and the coarse planes floor(zl/2) (EA) and
-    // floor(zl/2) + 1 (EB), all clamped into the coarse grid.
+    // cya .. cya + RPW/2 with cya = (gyw - 1) / 2, and the coarse planes floor(zl/2) (CA) and
+    // floor(zl/2) + 1 (CB, odd zl only), all clamped into the coarse grid, loaded with the
+    // fine plane into its prefetch buffer.
+    // (Byte offsets: coarse rows uniform, coarse columns per lane.)
     constexpr int CR = RPW / 2 + 1;
-    T EA[CR][2], EB[CR][2];
-    int ccx[2];
-    size_t crow[CR];
+    T CA[PD][CR][2], CB[PD][CR][2];
+    uint32_t ccb[2] = {0, 0}, crb[CR];
+    const uint32_t cplaneb = (uint32_t)((size_t)nc * (size_t)nc * sizeof(T));
     if (IN == kInProlong) {
       const int cxa = (gxa - 1) >> 1;
-      ccx[0] = min(max(cxa, 0), nc - 1);
-      ccx[1] = min(max(cxa + 1, 0), nc - 1);
+      ccb[0] = (uint32_t)min(max(cxa, 0), nc - 1) * (uint32_t)sizeof(T);
+      ccb[1] = (uint32_t)min(max(cxa + 1, 0), nc - 1) * (uint32_t)sizeof(T);
       const int cya = (gyw - 1) >> 1;
 #pragma unroll
-      for (int r = 0; r < CR; ++r) crow[r] = (size_t)min(max(cya + r, 0), nc - 1) * (size_t)nc;
+      for (int r = 0; r < CR; ++r)
+        crb[r] = (uint32_t)(min(max(cya + r, 0), nc - 1) * nc) * (uint32_t)sizeof(T);
     }
-    const size_t nc2 = (size_t)nc * (size_t)nc;
     auto load_coarse = [&](T (&E)[CR][2], int cz) {
-      const size_t zo = (size_t)min(max(cz, 0), nc - 1) * nc2;
+      const PlaneBuf be = plane_buf(ec, (size_t)min(max(cz, 0), nc - 1) * cplaneb, cplaneb);
 #pragma unroll
       for (int r = 0; r < CR; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) E[r][c] = ec[zo + crow[r] + ccx[c]];
+        for (int c = 0; c < 2; ++c) E[r][c] = buf_load<T>(be, ccb[c], crb[r]);
     };
-    bool first_load = true;
 
-    auto load = [&](int zl) {
+    // Loads of plane zl (parity ZP, known at compile time: see the step below) into
+    // prefetch buffer BUF.
+    auto load = [&](int zl, auto ZPC, auto BUFC) {
+      constexpr int zp = decltype(ZPC)::value;
+      constexpr int bf_ = decltype(BUFC)::value;
       const size_t zc = (size_t)min(max(zl, 0), n - 1);
       if constexpr (IN == kInProlong) {
-        // keep EA = plane floor(zl/2), EB = plane floor(zl/2) + 1 (needed for odd zl)
-        if (first_load) {
-          load_coarse(EA, zl >> 1);
-          load_coarse(EB, (zl >> 1) + 1);
-          first_load = false;
-        } else if (zl & 1) {
-          load_coarse(EB, (zl >> 1) + 1);
-        } else {
-#pragma unroll
-          for (int r = 0; r < CR; ++r)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) EA[r][c] = EB[r][c];
-        }
+        load_coarse(CA[bf_], zl >> 1);
+        if constexpr (zp == 1) load_coarse(CB[bf_], (zl >> 1) + 1);
       }
       const size_t zb = zc * planeb;
       const PlaneBuf bu = plane_buf(uin, zb, planeb), bf = plane_buf(f, zb, planeb);
@@ -180,9 +178,9 @@ struct Tiled {
       for (int i = 0; i < RPW; ++i) {
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          PU[i][o] = IN == kInZero ? T(0) : buf_load<T>(bu, cxb[o], rowb[i]);
-          PF[i][o] = buf_load<T>(bf, cxb[o], rowb[i]);
-          if (VAR) PK[i][o] = buf_load<T>(bk, cxb[o], rowb[i]);
+          PU[bf_][i][o] = IN == kInZero ? T(0) : buf_load<T>(bu, cxb[o], rowb[i]);
+          PF[bf_][i][o] = buf_load<T>(bf, cxb[o], rowb[i]);
+          if constexpr (VAR) PK[bf_][i][o] = buf_load<T>(bk, cxb[o], rowb[i]);
         }
       }
     };
@@ -191,18 +189,20 @@ struct Tiled {
     // waits on them early; in kInProlong it gains the interpolated coarse-grid correction
     // P ec on interior nodes (coarse rows of a fine row
     // i: i/2, i/2+1 for even i (odd fine y), (i+1)/2 for odd i; coarse columns cxa, cxa+1 for
-    // column 0 (odd fine x), cxa+1 for column 1; coarse planes EA (and EB for odd zl)).
-    auto insert = [&](int zl, auto S0C) {
+    // column 0 (odd fine x), cxa+1 for column 1; coarse planes CA (and CB for odd zl)).
+    auto insert = [&](int zl, auto S0C, auto ZPC, auto BUFC) {
       constexpr int s0 = decltype(S0C)::value;
+      constexpr int zp = decltype(ZPC)::value;
+      constexpr int bf_ = decltype(BUFC)::value;
       const bool zin = zl >= 1 && zl <= n - 2;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          T v = PU[i][o];
+          T v = PU[bf_][i][o];
           if constexpr (IN == kInProlong) {
-            const int mz = (zl & 1) ? 2 : 1;
-            const T wz = (zl & 1) ? T(0.5) : T(1);
+            constexpr int mz = zp ? 2 : 1;
+            const T wz = zp ? T(0.5) : T(1);
             const int my = (i % 2 == 0) ? 2 : 1;
             const int rb = (i % 2 == 0) ? i / 2 : (i + 1) / 2;
             const T wy = (i % 2 == 0) ? T(0.5) : T(1);
@@ -217,14 +217,15 @@ struct Tiled {
               for (int b2 = 0; b2 < my; ++b2)
 #pragma unroll
                 for (int c2 = 0; c2 < mx; ++c2)
-                  sum = sum + (wz * wy * wx) * (a2 == 0 ? EA[rb + b2][cb + c2] : EB[rb + b2][cb + c2]);
+                  sum = sum + (wz * wy * wx) * (a2 == 0 ? CA[bf_][rb + b2][cb + c2]
+                                                        : CB[bf_][rb + b2][cb + c2]);
             }
             const bool in = zin && ((upd >> (2 * i + o)) & 1u);
             if (in) v = v + sum;
           }
           U[s0][i][o] = v;
-          F[s0][i][o] = PF[i][o];
-          if (VAR) K[s0][i][o] = PK[i][o];
+          F[s0][i][o] = PF[bf_][i][o];
+          if constexpr (VAR) K[s0][i][o] = PK[bf_][i][o];
         }
     };
 
@@ -243,26 +244,37 @@ struct Tiled {
 
     const int zbeg = z0 - H, zend = z1 + H;  // planes loaded: [zbeg, zend)
     int zl = zbeg;
-    int step = 0;
-    load(zl);
+    load(zl, IC<(B0 + 1) & 1>{}, IC<0>{});
+    if constexpr (PD == 2) load(zl + 1, IC<B0 & 1>{}, IC<1>{});
 
     // One step for phase P = step mod Q: the plane zl - d sits in queue slot (P - d) mod Q.
     // The update column of row i in this step is o_i = (B0 + i + P) & 1, because the
     // colour of (x, y, p) is (x + y + p) & 1 and, at stage j, colour j&1 and p = zl-1-j
-    // make x's parity depend on zl only.
+    // make x's parity depend on zl only.  Tile origins are odd, so B0 = (z0 - 1) & 1, and
+    // zl = z0 - H + step with H and Q even: zl has the parity (B0 + 1 + P) & 1, and the
+    // step that of P.
     auto body = [&](auto PC) -> bool {
       constexpr int P = decltype(PC)::value;
       constexpr int s0 = imod(P, Q);
+      constexpr int zpar = (B0 + 1 + P) & 1;
+      constexpr int buf = PD == 2 ? (P & 1) : 0;
       // the prefetched plane zl enters the queue
-      insert(zl, IC<s0>{});
+      insert(zl, IC<s0>{}, IC<zpar>{}, IC<buf>{});
+      // Finish the inserted values here: left to the optimiser, the interpolation sinks
+      // to the first use in the stages, keeping the previous loads and partial sums live
+      // alongside the next plane's loads (an empty asm statement emits no instruction).
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) asm volatile("" : "+v"(U[s0][i][o]));
       __syncthreads();
       // Plane zl-1-H became final in the previous step and is still queued (slot
       // P-H-1): storing it here, just before the next loads, lets the stores complete in
       // the shadow of the loads instead of delaying the next step's wait for them.
       store(zl - 1 - H, IC<imod(P - H - 1, Q)>{});
-      if (zl + 1 < zend) load(zl + 1);
-      const int rb = (step + 1) & 1;  // LDS buffer written in the previous step
-      const int wb = step & 1;        // LDS buffer written in this step
+      if (zl + PD < zend) load(zl + PD, IC<PD == 2 ? zpar : 1 - zpar>{}, IC<buf>{});
+      constexpr int rb = (P + 1) & 1;  // LDS buffer written in the previous step
+      constexpr int wb = P & 1;        // LDS buffer written in this step
 
 #pragma unroll
       for (int j = 0; j < H; ++j) {
@@ -280,28 +292,28 @@ struct Tiled {
           if (o == 0) {
             xm = from_lane_below(U[cs][i][1]);
             xp = U[cs][i][1];
-            if (VAR) { kxm = from_lane_below(K[cs][i][1]); kxp = K[cs][i][1]; }
+            if constexpr (VAR) { kxm = from_lane_below(K[cs][i][1]); kxp = K[cs][i][1]; }
           } else {
             xm = U[cs][i][0];
             xp = from_lane_above(U[cs][i][0]);
-            if (VAR) { kxm = K[cs][i][0]; kxp = from_lane_above(K[cs][i][0]); }
+            if constexpr (VAR) { kxm = K[cs][i][0]; kxp = from_lane_above(K[cs][i][0]); }
           }
           // y-neighbours in column o: own rows, or the adjacent wave's edge row (the first
           // and the last wave read their own rows there: tile-edge values, never exact)
           T ym, yp, kym = T(0), kyp = T(0);
           if (i > 0) {
             ym = U[cs][i - 1][o];
-            if (VAR) kym = K[cs][i - 1][o];
+            if constexpr (VAR) kym = K[cs][i - 1][o];
           } else {
             ym = sh.eu[rb][pslot][wm][1][lane];
-            if (VAR) kym = sh.ek[rb][pslot][wm][1][lane];
+            if constexpr (VAR) kym = sh.ek[rb][pslot][wm][1][lane];
           }
           if (i < RPW - 1) {
             yp = U[cs][i + 1][o];
-            if (VAR) kyp = K[cs][i + 1][o];
+            if constexpr (VAR) kyp = K[cs][i + 1][o];
           } else {
             yp = sh.eu[rb][pslot][wp][0][lane];
-            if (VAR) kyp = sh.ek[rb][pslot][wp][0][lane];
+            if constexpr (VAR) kyp = sh.ek[rb][pslot][wp][0][lane];
           }
           const T zm = U[cm][i][o], zp = U[cp][i][o];
           const T h2f = h2 * F[cs][i][o];
@@ -328,19 +340,18 @@ struct Tiled {
           constexpr int i = 0;
           constexpr int o = (B0 + i + P) & 1;
           sh.eu[wb][pslot][w][0][lane] = U[sl][i][o];
-          if (VAR) sh.ek[wb][pslot][w][0][lane] = K[sl][i][o];
+          if constexpr (VAR) sh.ek[wb][pslot][w][0][lane] = K[sl][i][o];
         }
         {
           constexpr int i = RPW - 1;
           constexpr int o = (B0 + i + P) & 1;
           sh.eu[wb][pslot][w][1][lane] = U[sl][i][o];
-          if (VAR) sh.ek[wb][pslot][w][1][lane] = K[sl][i][o];
+          if constexpr (VAR) sh.ek[wb][pslot][w][1][lane] = K[sl][i][o];
         }
       }
 
       // the last step stores its own finished plane zl - H
       if (zl + 1 == zend) store(zl - H, IC<imod(P - H, Q)>{});
-      ++step;
       ++zl;
       return zl < zend;
     };
@@ -358,13 +369,13 @@ struct Tiled {
   }
 };
 
-template <typename T, bool VAR, int S, int W, int RPW, int IN>
+template <typename T, bool VAR, int S, int W, int RPW, int PD, int IN>
 __global__ void __launch_bounds__(64 * W)
     k_rbgs_tiled(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
                  const T* __restrict__ k, const T* __restrict__ ec, int nc, int n, T h2,
                  int tiles_x, int tiles_y, int zlen)
 {
-  using C = Tiled<T, VAR, S, W, RPW>;
+  using C = Tiled<T, VAR, S, W, RPW, PD>;
   __shared__ typename C::Shared sh;
   // XCD-aware tile index: workgroup b runs on XCD b % 8; XCD x gets tiles
   // [start_x, start_x + count_x) in order.
@@ -438,27 +449,60 @@ LaunchShape shape_for(int n, int capacity)
   return L;
 }
 
-template <typename T, bool VAR, int S, int W, int RPW, int IN>
+// Tile shape (waves x rows per wave) and prefetch depth per pass, from timing sweeps on
+// MI355X at 513^3: the second prefetch buffer is used wherever it keeps the occupancy.
+#ifndef MG_SMOOTH_W
+#define MG_SMOOTH_W 8
+#endif
+#ifndef MG_SMOOTH_RPW
+#define MG_SMOOTH_RPW 4
+#endif
+#ifndef MG_SMOOTH32_PROLONG_W
+#define MG_SMOOTH32_PROLONG_W 12
+#endif
+#ifndef MG_SMOOTH32_PROLONG_PD
+#define MG_SMOOTH32_PROLONG_PD 2
+#endif
+#ifndef MG_SMOOTH32_ZERO_PD
+#define MG_SMOOTH32_ZERO_PD 2
+#endif
+#ifndef MG_SMOOTH64_ZERO_PD
+#define MG_SMOOTH64_ZERO_PD 2
+#endif
+template <typename T, bool VAR, int S, int IN>
+struct Shape {
+  static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
+  static constexpr int W = (f32 && plain && IN == kInProlong) ? MG_SMOOTH32_PROLONG_W : MG_SMOOTH_W;
+  static constexpr int RPW = MG_SMOOTH_RPW;
+  static constexpr int PD = !plain ? 1
+                            : IN == kInProlong ? (f32 ? MG_SMOOTH32_PROLONG_PD : 1)
+                            : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
+                                               : 1;
+};
+
+template <typename T, bool VAR, int S, int IN>
 void launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
                const T* ec)
 {
-  using C = Tiled<T, VAR, S, W, RPW>;
-  auto kern = k_rbgs_tiled<T, VAR, S, W, RPW, IN>;
+  using Sh = Shape<T, VAR, S, IN>;
+  constexpr int W = Sh::W, RPW = Sh::RPW, PD = Sh::PD;
+  using C = Tiled<T, VAR, S, W, RPW, PD>;
+  auto kern = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN>;
   const LaunchShape L = shape_for<C>(n, resident_capacity(kern, 64 * W));
   const T h2 = (T)(h * h);
   const int nc = (n - 1) / 2 + 1;
   kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, L.tiles_x, L.tiles_y, L.zlen);
 }
 
-template <typename T, bool VAR, int S, int W, int RPW>
+template <typename T, bool VAR, int S>
 void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
                 bool zero_in, const T* ec)
 {
   if (ec) {
     // only FP32 passes fuse the prolongation (rbgs_tiled_fuses_prolong)
-    if constexpr (sizeof(T) == 4) launch_in<T, VAR, S, W, RPW, kInProlong>(s, n, h, k, f, uin, uout, ec);
-  } else if (zero_in) launch_in<T, VAR, S, W, RPW, kInZero>(s, n, h, k, f, uin, uout, ec);
-  else launch_in<T, VAR, S, W, RPW, kInRead>(s, n, h, k, f, uin, uout, ec);
+    if constexpr (sizeof(T) == 4) launch_in<T, VAR, S, kInProlong>(s, n, h, k, f, uin, uout, ec);
+  } else if (zero_in) launch_in<T, VAR, S, kInZero>(s, n, h, k, f, uin, uout, ec);
+  else launch_in<T, VAR, S, kInRead>(s, n, h, k, f, uin, uout, ec);
 }
 
 }  // namespace
@@ -480,15 +524,6 @@ int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
   return (var && value_bytes == 8) ? 1 : 2;
 }
 
-// Tile shape: waves per workgroup x rows per wave (tile height = their product).
-#ifndef MG_SMOOTH_W
-#define MG_SMOOTH_W 8
-#endif
-#ifndef MG_SMOOTH_RPW
-#define MG_SMOOTH_RPW 4
-#endif
-constexpr int kSW = MG_SMOOTH_W, kSR = MG_SMOOTH_RPW;
-
 template <typename T>
 void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
                 int sweeps, bool zero_in, const T* ec)
@@ -496,13 +531,13 @@ void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T*
   // the host asks for 2 sweeps with k only in FP32 (rbgs_tiled_max_sweeps)
   if (sweeps == 2) {
     if (k) {
-      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
+      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2>(s, n, h, k, f, uin, uout, zero_in, ec);
     } else {
-      launch_cfg<T, false, 2, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
+      launch_cfg<T, false, 2>(s, n, h, k, f, uin, uout, zero_in, ec);
     }
   } else {
-    if (k) launch_cfg<T, true, 1, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
-    else launch_cfg<T, false, 1, kSW, kSR>(s, n, h, k, f, uin, uout, zero_in, ec);
+    if (k) launch_cfg<T, true, 1>(s, n, h, k, f, uin, uout, zero_in, ec);
+    else launch_cfg<T, false, 1>(s, n, h, k, f, uin, uout, zero_in, ec);
   }
 }
 

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import MG_ENOCONV, MG_F32_IR, MG_F64, MgGrid, check, lib
+from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_TAIL, FUSE_ZERO,  # noqa: F401
+                   MG_ENOCONV, MG_F32_IR, MG_F64, MgGrid, check, lib)
 
 
 @dataclass
@@ -198,10 +199,12 @@ class Multigrid:
                                             ctypes.byref(out)))
         return out.value
 
-    def set_fusion(self, enable: bool):
-        """True (default): temporally blocked smoother on large 3D levels and the one-launch
-        coarse tail; False: per-colour smoother and one launch per step (diagnostics)."""
-        self._check(lib().mg_set_fusion(self.ctx, int(bool(enable))))
+    def set_fusion(self, flags=True):
+        """Kernel-fusion flags (mg_set_fusion): True = all (the default), False = none, or
+        an int OR of FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL."""
+        if isinstance(flags, bool):
+            flags = FUSE_ALL if flags else 0
+        self._check(lib().mg_set_fusion(self.ctx, int(flags)))
 
     def close(self):
         if self._ctx is not None:
