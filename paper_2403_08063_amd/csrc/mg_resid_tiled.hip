@@ -463,10 +463,13 @@ constexpr int restrict_pd()
 }
 // The FP64 variable-coefficient restriction holds k as well: 12 waves of 2 rows keep it
 // within the register file.
+#ifndef MG_RESTRICT32_W
+#define MG_RESTRICT32_W 8
+#endif
 template <typename T, bool VAR>
 constexpr int restrict_w()
 {
-  return (VAR && sizeof(T) == 8) ? 12 : kW;
+  return (VAR && sizeof(T) == 8) ? 12 : (sizeof(T) == 4 && !VAR) ? MG_RESTRICT32_W : kW;
 }
 template <typename T, bool VAR>
 constexpr int restrict_rpw()
@@ -496,12 +499,13 @@ void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const 
   };
   constexpr int pv = restrict_pd<T, true>(), pc = restrict_pd<T, false>();
   constexpr int wv = restrict_w<T, true>(), rv = restrict_rpw<T, true>();
+  constexpr int wc = restrict_w<T, false>();
   if (k)
     launch(k_stream<T, true, kRestrict, wv, rv, pv>,
            typename Stream<T, true, kRestrict, wv, rv, pv>::Args{}, wv, rv);
   else
-    launch(k_stream<T, false, kRestrict, kW, kRPW, pc>,
-           typename Stream<T, false, kRestrict, kW, kRPW, pc>::Args{}, kW, kRPW);
+    launch(k_stream<T, false, kRestrict, wc, kRPW, pc>,
+           typename Stream<T, false, kRestrict, wc, kRPW, pc>::Args{}, wc, kRPW);
 }
 
 namespace {

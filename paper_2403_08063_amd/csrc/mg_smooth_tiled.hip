@@ -469,15 +469,27 @@ LaunchShape shape_for(int n, int capacity)
 #ifndef MG_SMOOTH64_ZERO_PD
 #define MG_SMOOTH64_ZERO_PD 2
 #endif
+#ifndef MG_SMOOTH32_ZERO_W
+#define MG_SMOOTH32_ZERO_W 8
+#endif
+#ifndef MG_SMOOTH32_READ_W
+#define MG_SMOOTH32_READ_W 12
+#endif
+#ifndef MG_SMOOTH32_READ_PD
+#define MG_SMOOTH32_READ_PD 2
+#endif
 template <typename T, bool VAR, int S, int IN>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
-  static constexpr int W = (f32 && plain && IN == kInProlong) ? MG_SMOOTH32_PROLONG_W : MG_SMOOTH_W;
+  static constexpr int W = !(f32 && plain)   ? MG_SMOOTH_W
+                           : IN == kInProlong ? MG_SMOOTH32_PROLONG_W
+                           : IN == kInZero    ? MG_SMOOTH32_ZERO_W
+                                              : MG_SMOOTH32_READ_W;
   static constexpr int RPW = MG_SMOOTH_RPW;
   static constexpr int PD = !plain ? 1
                             : IN == kInProlong ? (f32 ? MG_SMOOTH32_PROLONG_PD : 1)
                             : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
-                                               : 1;
+                                               : (f32 ? MG_SMOOTH32_READ_PD : 1);
 };
 
 template <typename T, bool VAR, int S, int IN>
