@@ -130,6 +130,60 @@ def summarize_pmc(fetch_dir: str, write_dir: str, n: int):
     print(json.dumps(rec, indent=1))
 
 
+def _short_kernel_name(name: str) -> str:
+    name = name.replace("void ", "").replace("mgk::(anonymous namespace)::", "")
+    depth, out = 0, []
+    for ch in name:  # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` run of this script: the
+    per-kernel table and the mean duration of the fine-level FP64 smoother launches (the
+    largest grid of k_rbgs_tiled<double, ...>), beside bench.py's own HIP-event figure."""
+    import csv
+    import glob
+
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    trace = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not stats or not trace:
+        raise SystemExit(f"no kernel_stats / kernel_trace csv under {trace_dir}")
+    rows = list(csv.DictReader(open(stats[0])))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        t = float(r["TotalDurationNs"])
+        lines.append(f"| `{_short_kernel_name(r['Name'])}` | {r['Calls']} | {t / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {100 * t / total:.1f}% |")
+    launches = []
+    for r in csv.DictReader(open(trace[0])):
+        if SMOOTHER_KERNEL + "<double" in r["Kernel_Name"]:
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            launches.append((grid, _short_kernel_name(r["Kernel_Name"]),
+                             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    head = []
+    if launches:
+        gmax = max(g for g, _, _ in launches)
+        fine = [(k, d) for g, k, d in launches if g == gmax]
+        names = sorted({k for k, _ in fine})
+        mean = sum(d for _, d in fine) / len(fine)
+        head.append(f"Fine-level launches (largest grid) of `{'`, `'.join(names)}` in the trace: "
+                    f"{len(fine)}, mean duration {mean:.1f} us")
+        if bench_log:
+            for line in open(bench_log):
+                if line.startswith("{"):
+                    rec = json.loads(line)
+                    head[-1] += (f" (bench.py's HIP-event average per launch in the same run: "
+                                 f"{rec['roofline']['launch_ms'] * 1e3:.1f} us)")
+        head[-1] += "."
+    print("\n".join(head + [""] + lines))
+
+
 def cpu_baseline(f_np, levels, fp64_cycles):
     import numpy as np
 
@@ -164,7 +218,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-trace", nargs="+", metavar=("TRACE_DIR", "BENCH_LOG"))
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace[:2])
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.n)
         return
@@ -254,7 +312,9 @@ def main():
         ev1.record(stream)
         ev1.synchronize()
         ms32.append(ev0.elapsed_time(ev1))
+    t_launch32 = float(np.median(ms32)) / launches
     glups32 = sweeps * interior / (float(np.median(ms32)) * 1e-3) / 1e9
+    achieved32 = 12 * interior / (t_launch32 * 1e-3) / 1e9  # read u, f; write u (float)
 
     traffic = measured_traffic(interior)
     value = float(np.median(t32))
@@ -299,6 +359,16 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": bytes_launch,
             "launch_ms": round(t_launch, 4),
+        },
+        "roofline_fp32_smoother": {
+            "kernel": f"{SMOOTHER_KERNEL}<float, 2 sweeps> (fine level)",
+            "bound": "hbm",
+            "achieved": round(achieved32, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved32 / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": 12 * interior,
+            "launch_ms": round(t_launch32, 4),
         },
     }
     if not args.no_cpu_baseline:
