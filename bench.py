@@ -316,6 +316,21 @@ def main():
     glups32 = sweeps * interior / (float(np.median(ms32)) * 1e-3) / 1e9
     achieved32 = 12 * interior / (t_launch32 * 1e-3) / 1e9  # read u, f; write u (float)
 
+    # achievable streaming bandwidth on this device: a plain 1 GiB device-to-device copy
+    # (read + write bytes), the practical ceiling beside the 8 TB/s peak
+    ca = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    cs = torch.cuda.current_stream()
+    mc = []
+    for _ in range(4):
+        ev0.record(cs)
+        cb.copy_(ca)
+        ev1.record(cs)
+        ev1.synchronize()
+        mc.append(ev0.elapsed_time(ev1))
+    copy_gbs = 2 * CALIB_BYTES / (min(mc[1:]) * 1e-3) / 1e9
+    del ca, cb
+
     traffic = measured_traffic(interior)
     value = float(np.median(t32))
     rec = {
@@ -359,6 +374,8 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": bytes_launch,
             "launch_ms": round(t_launch, 4),
+            "copy_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "roofline_fp32_smoother": {
             "kernel": f"{SMOOTHER_KERNEL}<float, 2 sweeps> (fine level)",
