@@ -158,16 +158,20 @@ mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, doubl
  *                   first post-smoothing pass (FP32 passes) instead of a separate pass;
  *  MG_FUSE_ZERO     a zero initial guess read as 0 by the first pre-smoothing pass instead
  *                   of being written first;
- *  MG_FUSE_TAIL     all levels with at most 4096 interior nodes in one launch.
- * Default MG_FUSE_ALL.  Clearing MG_FUSE_PROLONG, MG_FUSE_ZERO or MG_FUSE_TAIL leaves every
- * result bitwise unchanged; without MG_FUSE_BLOCKED smoothing results are unchanged but
+ *  MG_FUSE_TAIL     all levels with at most 4096 interior nodes in one launch;
+ *  MG_FUSE_RESTRICT on such large 3D levels, the residual and its full-weighting restriction
+ *                   computed inside the pre-smoothing pass (FP32 passes from a zero guess,
+ *                   constant coefficient) instead of a separate pass.
+ * Default MG_FUSE_ALL.  Clearing MG_FUSE_PROLONG, MG_FUSE_ZERO, MG_FUSE_TAIL or
+ * MG_FUSE_RESTRICT leaves every result bitwise unchanged; without MG_FUSE_BLOCKED smoothing results are unchanged but
  * residual sums are accumulated in another order.  EINVAL for bits outside MG_FUSE_ALL. */
 enum {
   MG_FUSE_BLOCKED = 1,
   MG_FUSE_PROLONG = 2,
   MG_FUSE_ZERO = 4,
   MG_FUSE_TAIL = 8,
-  MG_FUSE_ALL = 15
+  MG_FUSE_RESTRICT = 16,
+  MG_FUSE_ALL = 31
 };
 mg_status mg_set_fusion(mg_ctx* ctx, int flags);
 

@@ -11,8 +11,9 @@ iterative-refinement form and a differentiable variable-coefficient form.
 """
 from .solver import Multigrid, SolveInfo, default_levels  # noqa: F401
 from .autograd import MGSolve, solve  # noqa: F401
-from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_TAIL, FUSE_ZERO,  # noqa: F401
-                   MgError)
+from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_RESTRICT, FUSE_TAIL,  # noqa: F401
+                   FUSE_ZERO, MgError)
 
 __all__ = ["Multigrid", "SolveInfo", "MGSolve", "solve", "MgError", "default_levels",
-           "FUSE_ALL", "FUSE_BLOCKED", "FUSE_PROLONG", "FUSE_TAIL", "FUSE_ZERO"]
+           "FUSE_ALL", "FUSE_BLOCKED", "FUSE_PROLONG", "FUSE_RESTRICT", "FUSE_TAIL",
+           "FUSE_ZERO"]

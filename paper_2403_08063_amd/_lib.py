@@ -16,8 +16,8 @@ STATUS_NAMES = {0: "MG_OK", 1: "MG_EINVAL", 2: "MG_ENOMEM", 3: "MG_EHIP", 4: "MG
                 5: "MG_ENAN", 6: "MG_ESTATE"}
 MG_F64, MG_F32_IR = 0, 1
 # kernel-fusion flags (mg_set_fusion)
-FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL = 1, 2, 4, 8
-FUSE_ALL = 15
+FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL, FUSE_RESTRICT = 1, 2, 4, 8, 16
+FUSE_ALL = 31
 
 # every function declared in include/mg.h
 EXPORTS = [

@@ -192,7 +192,7 @@ bool use_tiled(const mg_ctx* c, int l)
 // to be 0 (a coarse-grid correction) and is not read.
 template <typename T>
 T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool zero_guess,
-          const T* ec = nullptr)
+          const T* ec = nullptr, T* fc = nullptr)
 {
   const Level& L = c->lv[l];
   const int dim = c->g.dim;
@@ -218,7 +218,8 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
     const int maxsw = mgk::rbgs_tiled_max_sweeps(k != nullptr, sizeof(T));
     while (left > 0) {
       const int sw = left >= maxsw ? maxsw : left;
-      mgk::rbgs_tiled<T>(c->s, L.n, L.h, k, f, cur, other, sw, zero, ec);
+      // fc: the residual restriction rides on the (single) pre-smoothing pass
+      mgk::rbgs_tiled<T>(c->s, L.n, L.h, k, f, cur, other, sw, zero, ec, left == sw ? fc : nullptr);
       T* x = cur;
       cur = other;
       other = x;
@@ -263,10 +264,18 @@ T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
     mgk::coarsest_solve<T>(c->s, dim, L.n, c->ainv, f, u);
     return u;
   }
-  T* cur = smooth<T>(c, l, u, t, f, V.k, c->g.nu1, zero_guess);
   const View<T> C = view<T>(c, l + 1);
-  if (use_tiled(c, l)) mgk::restrict_residual_tiled<T>(c->s, L.n, L.h, V.k, f, cur, C.f);
-  else mgk::restrict_residual<T>(c->s, dim, L.n, L.h, V.k, f, cur, C.f);
+  // residual + restriction inside the pre-smoothing pass: one FP32 2-sweep pass from a zero
+  // guess with constant coefficients (rbgs_tiled_fuses_restrict)
+  const bool fuse_r = use_tiled(c, l) && (c->fuse & MG_FUSE_RESTRICT) &&
+                      (c->fuse & MG_FUSE_ZERO) && zero_guess && c->g.nu1 == 2 &&
+                      mgk::rbgs_tiled_max_sweeps(V.k != nullptr, sizeof(T)) == 2 &&
+                      mgk::rbgs_tiled_fuses_restrict(sizeof(T), V.k != nullptr);
+  T* cur = smooth<T>(c, l, u, t, f, V.k, c->g.nu1, zero_guess, nullptr, fuse_r ? C.f : nullptr);
+  if (!fuse_r) {
+    if (use_tiled(c, l)) mgk::restrict_residual_tiled<T>(c->s, L.n, L.h, V.k, f, cur, C.f);
+    else mgk::restrict_residual<T>(c->s, dim, L.n, L.h, V.k, f, cur, C.f);
+  }
   T* ec = cycle<T>(c, l + 1, C.u, C.t, C.f, true);
   // u += P ec, fused into the first post-smoothing pass on large 3D levels (FP32)
   T* other = cur == u ? t : u;

@@ -20,15 +20,20 @@ void rbgs_colour(hipStream_t s, int dim, int n, double h, const T* k, const T* f
 // `sweeps` (1 or 2) full red-black sweeps fused in one pass over a 3D level, out of place:
 // uout = RBGS^sweeps(uin).  zero_in: treat uin as identically 0 (not read).  ec != nullptr:
 // the input is uin + P ec (coarse-grid correction with (n-1)/2+1 nodes per side, added on
-// interior nodes as prolong_add does).  The boundary of uout is not written.
+// interior nodes as prolong_add does).  fc != nullptr (2 sweeps from a zero guess, FP32,
+// constant coefficient: rbgs_tiled_fuses_restrict): the pass also writes the full-weighting
+// restriction of the residual f - A uout to the interior of fc, the next coarser level's
+// right-hand side, with the arithmetic of restrict_residual_tiled.  The boundary of uout
+// (and of fc) is not written.
 template <typename T>
 void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin,
-                T* uout, int sweeps, bool zero_in, const T* ec = nullptr);
+                T* uout, int sweeps, bool zero_in, const T* ec = nullptr, T* fc = nullptr);
 // Whether the fused pass serves this level (3D, large enough for its tiles), and how many
 // sweeps one pass may fuse.
 bool rbgs_tiled_supported(int dim, int n);
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes);
 bool rbgs_tiled_fuses_prolong(size_t value_bytes);
+bool rbgs_tiled_fuses_restrict(size_t value_bytes, bool var);
 
 // r = f - A u (interior), 0 on the boundary.
 template <typename T>

@@ -49,21 +49,33 @@ enum { kInRead = 0, kInZero = 1, kInProlong = 2 };
 
 constexpr int imod(int a, int m) { return ((a % m) + m) % m; }
 
-template <typename T, bool VAR, int S, int W, int RPW, int PD>
+// RES = 1: the pass also computes the residual f - A u of the smoothed iterate and its
+// full-weighting restriction onto the next coarser level (the smoother's output stays in
+// registers instead of being read back by a separate restriction pass).  The residual of
+// plane q needs the final planes q-1, q, q+1, so it runs one step after plane q+1 became
+// final: two more queued planes, a 4-node wider tile overlap in x and y (the residual is
+// exact one node, its full weighting two nodes further inside than the final values) and
+// 2 more final planes at each end of the z-chunk.
+template <typename T, bool VAR, int S, int W, int RPW, int PD, int RES = 0>
 struct Tiled {
   static_assert(PD == 1 || PD == 2, "prefetch depth");
+  static_assert(RES == 0 || (!VAR && S == 2), "the fused restriction serves the plain 2-sweep pass");
   static constexpr int H = 2 * S;        // halo = number of stages
   static constexpr int BX = 128;         // columns per tile (2 per lane)
   static constexpr int BY = W * RPW;     // rows per tile
-  static constexpr int TXO = BX - 2 * H; // output columns per tile
-  static constexpr int TYO = BY - 2 * H; // output rows per tile
-  static constexpr int Q = H + 2;        // planes held per lane
+  static constexpr int XR = RES ? 4 : 0; // extra overlap for the fused restriction
+  static constexpr int ZR = RES ? 2 : 0; // extra final planes at each end of a z-chunk
+  static constexpr int TXO = BX - 2 * H - XR; // output columns per tile (tile stride)
+  static constexpr int TYO = BY - 2 * H - XR; // output rows per tile
+  static constexpr int Q = H + 2 + (RES ? 2 : 0);  // planes held per lane (even)
   static_assert(RPW % 2 == 0, "row parity must be uniform across the waves of a tile");
   static_assert(TYO > 0, "tile too short for the halo");
 
   struct Shared {
     T eu[2][H][W][2][64];                    // wave-boundary rows of u
     T ek[VAR ? 2 : 1][VAR ? H : 1][W][2][64]; // and of k
+    T er[RES ? 2 : 1][RES ? W : 1][2][2][64]; // RES: both columns of a final plane's edge rows
+    T erx[RES ? 2 : 1][RES ? W : 1][64];      // RES: x-filtered residual of a wave's first row
   };
 
   // The first column of every lane and the first row of every wave have odd global
@@ -79,7 +91,7 @@ struct Tiled {
                                              const T* __restrict__ f, const T* __restrict__ k,
                                              const T* __restrict__ ec, int nc,
                                              int n, T h2, int ox, int oy, int z0, int z1,
-                                             Shared& sh)
+                                             T ih2, T* __restrict__ fc, Shared& sh)
   {
     const int lane = threadIdx.x & 63;
     // wave index, made explicitly wave-uniform so that row bookkeeping stays scalar
@@ -102,7 +114,7 @@ struct Tiled {
     for (int o = 0; o < 2; ++o) {
       const int gx = gxa + o, px = 2 * lane + o;
       const bool cin = gx >= 1 && gx <= n - 2;
-      const bool cout = cin && px >= H && px <= BX - 1 - H;
+      const bool cout = cin && px >= H && px < H + TXO;
       cxb[o] = (uint32_t)min(max(gx, 0), n - 1) * (uint32_t)sizeof(T);
       sxb[o] = cout ? cxb[o] : 0x80000000u;
 #pragma unroll
@@ -114,7 +126,7 @@ struct Tiled {
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int gy = gyw + i, pr = w * RPW + i;
-      rowout |= (gy >= 1 && gy <= n - 2 && pr >= H && pr <= BY - 1 - H) ? 1u << i : 0u;
+      rowout |= (gy >= 1 && gy <= n - 2 && pr >= H && pr < H + TYO) ? 1u << i : 0u;
       rowb[i] = (uint32_t)(min(max(gy, 0), n - 1) * n) * (uint32_t)sizeof(T);
     }
     const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * sizeof(T));
@@ -242,8 +254,30 @@ struct Tiled {
       }
     };
 
-    const int zbeg = z0 - H, zend = z1 + H;  // planes loaded: [zbeg, zend)
+    const int zbeg = z0 - H - ZR, zend = z1 + H + ZR;  // planes loaded: [zbeg, zend)
+    // RES: one more step completes the restriction of the last residual plane
+    const int zstop = zend + (RES ? 1 : 0);
     int zl = zbeg;
+
+    // Fused restriction (RES): lane column 1 is the even fine column 2X of coarse column X
+    // (tile origins are odd), rows with odd i are the even fine rows 2Y.  Coarse nodes owned
+    // by this tile: 2X in [ox + 2, ox + 2 + TXO), from 2 in the first tile (ox = 1), 2Y
+    // likewise, 2Z in [z0, z1) -- a partition of the coarse interior.  Each lies at least 6
+    // nodes inside the loaded tile, or next to the grid boundary, whose values are exact.
+    const int gxc = gxa + 1;
+    const int xlo = ox == 1 ? 2 : ox + 2, ylo = oy == 1 ? 2 : oy + 2;
+    const bool cown = RES && gxc >= xlo && gxc < ox + 2 + TXO && gxc <= n - 3;
+    unsigned crown = 0;
+#pragma unroll
+    for (int i = 1; i < RPW; i += 2) {
+      const int gy = gyw + i;
+      crown |= (gy >= ylo && gy < oy + 2 + TYO && gy <= n - 3) ? 1u << i : 0u;
+    }
+    T rxprev[RPW], acc[RPW / 2];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) rxprev[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < RPW / 2; ++i) acc[i] = T(0);
     load(zl, IC<(B0 + 1) & 1>{}, IC<0>{});
     if constexpr (PD == 2) load(zl + 1, IC<B0 & 1>{}, IC<1>{});
 
@@ -251,8 +285,75 @@ struct Tiled {
     // The update column of row i in this step is o_i = (B0 + i + P) & 1, because the
     // colour of (x, y, p) is (x + y + p) & 1 and, at stage j, colour j&1 and p = zl-1-j
     // make x's parity depend on zl only.  Tile origins are odd, so B0 = (z0 - 1) & 1, and
-    // zl = z0 - H + step with H and Q even: zl has the parity (B0 + 1 + P) & 1, and the
-    // step that of P.
+    // zl = z0 - H - ZR + step with H, ZR and Q even: zl has the parity (B0 + 1 + P) & 1,
+    // and the step that of P.
+    // RES, at the end of step zl (phase P): (1) full weighting in y and z of the residual
+    // plane zl-H-2, x-filtered in the previous step; (2) residual of plane q = zl-H-1 (its
+    // neighbours q-1, q, q+1 are final) and its full weighting in x; (3) both columns of the
+    // edge rows of the plane zl-H that became final in this step, for the next step's
+    // residual.  Same operations, in the same order, as the stand-alone restriction pass.
+    auto restrict_step = [&](auto PC) {
+      constexpr int P = decltype(PC)::value;
+      constexpr int rb = (P + 1) & 1, wb = P & 1;
+      constexpr int zpar = (B0 + 1 + P) & 1;  // parity of zl, of zl-H-2 and of zl-H
+      const int qp = zl - H - 2;
+      if (qp >= z0 - 1 && qp <= z1) {
+        T ry[RPW / 2];
+#pragma unroll
+        for (int i = 1; i < RPW; i += 2) {
+          const T below = i + 1 < RPW ? rxprev[i + 1] : sh.erx[rb][wp][lane];
+          ry[i / 2] = (T(0.25) * rxprev[i - 1] + T(0.5) * rxprev[i]) + T(0.25) * below;
+        }
+        if constexpr (zpar == 1) {
+          // odd plane qp = 2Z+1 completes coarse plane Z and starts plane Z+1
+          const int Z = (qp - 1) >> 1;
+          const bool zown = 2 * Z >= z0 && 2 * Z < z1 && Z >= 1 && Z <= nc - 2;
+#pragma unroll
+          for (int i = 1; i < RPW; i += 2) {
+            const T done = acc[i / 2] + T(0.25) * ry[i / 2];
+            if (zown && cown && ((crown >> i) & 1u))
+              fc[((size_t)Z * nc + (size_t)((gyw + i) >> 1)) * (size_t)nc + (size_t)(gxc >> 1)] = done;
+            acc[i / 2] = T(0.25) * ry[i / 2];
+          }
+        } else {
+#pragma unroll
+          for (int i = 1; i < RPW; i += 2) acc[i / 2] = acc[i / 2] + T(0.5) * ry[i / 2];
+        }
+      }
+      const int q = zl - H - 1;
+      if (q >= z0 - 1 && q <= z1) {
+        constexpr int cq = imod(P - H - 1, Q), cm = imod(P - H - 2, Q), cp = imod(P - H, Q);
+        const bool zin = q >= 1 && q <= n - 2;
+        T r[RPW][2];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const T l1 = from_lane_below(U[cq][i][1]);
+          const T r0 = from_lane_above(U[cq][i][0]);
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const T xm = o == 0 ? l1 : U[cq][i][0];
+            const T xp = o == 0 ? U[cq][i][1] : r0;
+            const T ym = i > 0 ? U[cq][i - 1][o] : sh.er[rb][wm][1][o][lane];
+            const T yp = i < RPW - 1 ? U[cq][i + 1][o] : sh.er[rb][wp][0][o][lane];
+            const T au = au_const<T, 3>(ih2, U[cq][i][o], xm, xp, ym, yp, U[cm][i][o], U[cp][i][o]);
+            const T rv = F[cq][i][o] - au;
+            // fine nodes outside the interior carry no residual
+            r[i][o] = (zin && ((upd >> (2 * i + o)) & 1u)) ? rv : T(0);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+          rxprev[i] = (T(0.25) * r[i][0] + T(0.5) * r[i][1]) + T(0.25) * from_lane_above(r[i][0]);
+        sh.erx[wb][w][lane] = rxprev[0];
+      }
+      constexpr int cf = imod(P - H, Q);
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        sh.er[wb][w][0][o][lane] = U[cf][0][o];
+        sh.er[wb][w][1][o][lane] = U[cf][RPW - 1][o];
+      }
+    };
+
     auto body = [&](auto PC) -> bool {
       constexpr int P = decltype(PC)::value;
       constexpr int s0 = imod(P, Q);
@@ -350,10 +451,11 @@ struct Tiled {
         }
       }
 
+      if constexpr (RES) restrict_step(IC<P>{});
       // the last step stores its own finished plane zl - H
       if (zl + 1 == zend) store(zl - H, IC<imod(P - H, Q)>{});
       ++zl;
-      return zl < zend;
+      return zl < zstop;
     };
 
     auto unrolled = [&](auto... PCs) {
@@ -369,13 +471,13 @@ struct Tiled {
   }
 };
 
-template <typename T, bool VAR, int S, int W, int RPW, int PD, int IN>
+template <typename T, bool VAR, int S, int W, int RPW, int PD, int IN, int RES>
 __global__ void __launch_bounds__(64 * W)
     k_rbgs_tiled(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
                  const T* __restrict__ k, const T* __restrict__ ec, int nc, int n, T h2,
-                 int tiles_x, int tiles_y, int zlen)
+                 T ih2, T* __restrict__ fc, int tiles_x, int tiles_y, int zlen)
 {
-  using C = Tiled<T, VAR, S, W, RPW, PD>;
+  using C = Tiled<T, VAR, S, W, RPW, PD, RES>;
   __shared__ typename C::Shared sh;
   // XCD-aware tile index: workgroup b runs on XCD b % 8; XCD x gets tiles
   // [start_x, start_x + count_x) in order.
@@ -391,8 +493,8 @@ __global__ void __launch_bounds__(64 * W)
   // parity of (x of column 0) + (y of row 0) + z0 - 1; RPW is even, so it is the same
   // for every wave's first row
   const int b0 = ((ox - C::H) + (oy - C::H) + z0 - 1) & 1;
-  if (b0) C::template run<1, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, sh);
-  else C::template run<0, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, sh);
+  if (b0) C::template run<1, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, sh);
+  else C::template run<0, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, sh);
 }
 
 struct LaunchShape {
@@ -420,7 +522,7 @@ int resident_capacity(Kernel kernel, int block)
 }
 
 // Tiles cover the interior in x and y; z is cut into chunks.  Each chunk costs its length
-// plus 2H warm-up planes, and workgroups run in rounds of `capacity`; the chunk count that
+// plus 2(H + ZR) warm-up planes, and workgroups run in rounds of `capacity`; the chunk count that
 // minimises (rounds x planes per workgroup) -- the critical path -- is chosen.
 template <typename C>
 LaunchShape shape_for(int n, int capacity)
@@ -438,7 +540,7 @@ LaunchShape shape_for(int n, int capacity)
     const int chunks = (m + zlen - 1) / zlen;
     const long long blocks = (long long)per * chunks;
     const long long rounds = (blocks + capacity - 1) / capacity;
-    const long long cost = rounds * (zlen + 2 * C::H);
+    const long long cost = rounds * (zlen + 2 * (C::H + C::ZR));
     if (best < 0 || cost < best) {
       best = cost;
       L.zlen = zlen;
@@ -478,32 +580,55 @@ LaunchShape shape_for(int n, int capacity)
 #ifndef MG_SMOOTH32_READ_PD
 #define MG_SMOOTH32_READ_PD 2
 #endif
-template <typename T, bool VAR, int S, int IN>
+#ifndef MG_SMOOTH32_RES_W
+#define MG_SMOOTH32_RES_W 8
+#endif
+#ifndef MG_SMOOTH32_RES_RPW
+#define MG_SMOOTH32_RES_RPW 6
+#endif
+#ifndef MG_SMOOTH32_PROLONG_RPW
+#define MG_SMOOTH32_PROLONG_RPW 4
+#endif
+#ifndef MG_SMOOTH32_READ_RPW
+#define MG_SMOOTH32_READ_RPW 4
+#endif
+#ifndef MG_SMOOTH32_RES_PD
+#define MG_SMOOTH32_RES_PD 2
+#endif
+template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
-  static constexpr int W = !(f32 && plain)   ? MG_SMOOTH_W
+  static constexpr int W = RES                ? MG_SMOOTH32_RES_W
+                           : !(f32 && plain)   ? MG_SMOOTH_W
                            : IN == kInProlong ? MG_SMOOTH32_PROLONG_W
                            : IN == kInZero    ? MG_SMOOTH32_ZERO_W
                                               : MG_SMOOTH32_READ_W;
-  static constexpr int RPW = MG_SMOOTH_RPW;
-  static constexpr int PD = !plain ? 1
+  static constexpr int RPW = RES                ? MG_SMOOTH32_RES_RPW
+                             : !(f32 && plain)   ? MG_SMOOTH_RPW
+                             : IN == kInProlong ? MG_SMOOTH32_PROLONG_RPW
+                             : IN == kInRead    ? MG_SMOOTH32_READ_RPW
+                                                : MG_SMOOTH_RPW;
+  static constexpr int PD = RES ? MG_SMOOTH32_RES_PD
+                            : !plain ? 1
                             : IN == kInProlong ? (f32 ? MG_SMOOTH32_PROLONG_PD : 1)
                             : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
                                                : (f32 ? MG_SMOOTH32_READ_PD : 1);
 };
 
-template <typename T, bool VAR, int S, int IN>
+template <typename T, bool VAR, int S, int IN, int RES = 0>
 void launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
-               const T* ec)
+               const T* ec, T* fc = nullptr)
 {
-  using Sh = Shape<T, VAR, S, IN>;
+  using Sh = Shape<T, VAR, S, IN, RES>;
   constexpr int W = Sh::W, RPW = Sh::RPW, PD = Sh::PD;
-  using C = Tiled<T, VAR, S, W, RPW, PD>;
-  auto kern = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN>;
+  using C = Tiled<T, VAR, S, W, RPW, PD, RES>;
+  auto kern = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN, RES>;
   const LaunchShape L = shape_for<C>(n, resident_capacity(kern, 64 * W));
   const T h2 = (T)(h * h);
   const int nc = (n - 1) / 2 + 1;
-  kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, L.tiles_x, L.tiles_y, L.zlen);
+  const T ih2 = (T)(1.0 / (h * h));
+  kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, ih2, fc, L.tiles_x, L.tiles_y,
+                                   L.zlen);
 }
 
 template <typename T, bool VAR, int S>
@@ -536,10 +661,26 @@ int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
   return (var && value_bytes == 8) ? 1 : 2;
 }
 
+bool rbgs_tiled_fuses_restrict(size_t value_bytes, bool var)
+{
+  // the FP64 pass holding two more planes exceeds the register file
+  return value_bytes == 4 && !var;
+}
+
 template <typename T>
 void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
-                int sweeps, bool zero_in, const T* ec)
+                int sweeps, bool zero_in, const T* ec, T* fc)
 {
+  if (fc) {
+    // two sweeps from a zero guess with the residual restricted into fc; the host asks for
+    // it only where rbgs_tiled_fuses_restrict holds
+    if constexpr (sizeof(T) == 4) {
+      if (!k && sweeps == 2 && zero_in && !ec) {
+        launch_in<T, false, 2, kInZero, 1>(s, n, h, k, f, uin, uout, ec, fc);
+        return;
+      }
+    }
+  }
   // the host asks for 2 sweeps with k only in FP32 (rbgs_tiled_max_sweeps)
   if (sweeps == 2) {
     if (k) {
@@ -554,8 +695,8 @@ void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T*
 }
 
 template void rbgs_tiled<double>(hipStream_t, int, double, const double*, const double*,
-                                 const double*, double*, int, bool, const double*);
+                                 const double*, double*, int, bool, const double*, double*);
 template void rbgs_tiled<float>(hipStream_t, int, double, const float*, const float*,
-                                const float*, float*, int, bool, const float*);
+                                const float*, float*, int, bool, const float*, float*);
 
 }  // namespace mgk

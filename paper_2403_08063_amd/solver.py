@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_TAIL, FUSE_ZERO,  # noqa: F401
+from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_RESTRICT, FUSE_TAIL,  # noqa: F401
+                   FUSE_ZERO,
                    MG_ENOCONV, MG_F32_IR, MG_F64, MgGrid, check, lib)
 
 
@@ -201,7 +202,7 @@ class Multigrid:
 
     def set_fusion(self, flags=True):
         """Kernel-fusion flags (mg_set_fusion): True = all (the default), False = none, or
-        an int OR of FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL."""
+        an int OR of FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL, FUSE_RESTRICT."""
         if isinstance(flags, bool):
             flags = FUSE_ALL if flags else 0
         self._check(lib().mg_set_fusion(self.ctx, int(flags)))

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 from conftest import interior, relmax
-from paper_2403_08063_amd import FUSE_ALL, FUSE_PROLONG, FUSE_ZERO, Multigrid, inputs
+from paper_2403_08063_amd import FUSE_ALL, FUSE_PROLONG, FUSE_RESTRICT, FUSE_ZERO, Multigrid, inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -115,19 +115,21 @@ def test_coarse_tail_bitwise_equals_per_level_launches(dim, n, levels, var, prec
     assert np.array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("off", ["prolong", "zero"])
+@pytest.mark.parametrize("off", ["prolong", "zero", "restrict"])
 @pytest.mark.parametrize("prec", ["f64", "f32_ir"])
 @pytest.mark.parametrize("n,levels,var", [(161, 6, False), (321, 7, False), (161, 6, True)])
 def test_fused_passes_bitwise_equal_separate_passes(n, levels, var, prec, off):
     """On levels served by the blocked smoother, the coarse-grid correction added inside the
-    first post-smoothing pass and a zero initial guess read as 0 by the first pre-smoothing
-    pass reproduce the separate prolongation and fill passes bit for bit (at 321^3 the
-    second level, 161^3, takes the zero-guess pass in FP64 as well)."""
+    first post-smoothing pass, a zero initial guess read as 0 by the first pre-smoothing pass
+    and the residual restriction computed inside that pass reproduce the separate
+    prolongation, fill and restriction passes bit for bit (at 321^3 the second level,
+    161^3, takes the zero-guess pass in FP64 as well)."""
     say(f"fused passes n={n} var={var} prec={prec} off={off}")
     k = random_k(3, n, 32) if var else None
     f = dev(inputs.uniform_interior(3, n, 31))
     out = []
-    for flags in (FUSE_ALL, FUSE_ALL & ~(FUSE_PROLONG if off == "prolong" else FUSE_ZERO)):
+    drop = {"prolong": FUSE_PROLONG, "zero": FUSE_ZERO, "restrict": FUSE_RESTRICT}[off]
+    for flags in (FUSE_ALL, FUSE_ALL & ~drop):
         mg = Multigrid(3, n, levels, variable=var, precision=prec, device=DEV)
         mg.set_fusion(flags)
         if var:
@@ -423,4 +425,4 @@ def test_error_statuses():
     with pytest.raises(ValueError):
         mg2.solve(dev(f[:-1]))
     with pytest.raises(MgError, match="MG_EINVAL"):
-        mg2.set_fusion(16)
+        mg2.set_fusion(32)
