@@ -184,27 +184,51 @@ def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24):
     print("\n".join(head + [""] + lines))
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(f_np, levels, fp64_cycles):
+    """The oracle (OpenMP inside each colour) on the host cores: one FP64 V-cycle plus one
+    residual norm on the full workload, at all available threads and at one thread."""
+    import ctypes
+
     import numpy as np
 
     import oracle
 
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    threads = int(os.environ.get("OMP_NUM_THREADS", threads))
     oracle.build()
-    u = np.zeros_like(f_np)
-    t0 = time.perf_counter()
-    oracle.vcycle(f_np, u, levels)
-    r = oracle.residual(f_np, u)
-    oracle.interior_norm2(r)
-    t = time.perf_counter() - t0
+    gomp = ctypes.CDLL("libgomp.so.1")  # the oracle's OpenMP runtime
+
+    def sample(nthreads):
+        gomp.omp_set_num_threads(nthreads)
+        u = np.zeros_like(f_np)
+        t0 = time.perf_counter()
+        oracle.vcycle(f_np, u, levels)
+        oracle.interior_norm2(oracle.residual(f_np, u))
+        return time.perf_counter() - t0
+
+    t = sample(threads)
+    t1 = sample(1)
+    gomp.omp_set_num_threads(threads)
     return {
         "value": round(t * fp64_cycles * 1e3, 1),
         "unit": "ms",
-        "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"one FP64 V(2,2) cycle + one residual norm on the full {f_np.shape[0]}^3 "
-                  f"workload ({t:.2f} s), scaled by the FP64 cycle count ({fp64_cycles})",
+                  f"workload ({t:.2f} s at {threads} threads, {t1:.2f} s at 1), scaled by "
+                  f"the FP64 cycle count ({fp64_cycles})",
+        "value_1_thread": round(t1 * fp64_cycles * 1e3, 1),
+        "cpu_model": _cpu_model(),
     }
 
 
@@ -372,6 +396,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_gbs": round(traffic / (t_launch * 1e-3) / 1e9, 1) if traffic else None,
             "bytes_per_launch": bytes_launch,
             "launch_ms": round(t_launch, 4),
             "copy_gbs": round(copy_gbs, 1),
