@@ -17,6 +17,7 @@ namespace mgk {
 constexpr int kBufferWord3 = 0x00020000;
 
 typedef unsigned int BufU32x2 __attribute__((__vector_size__(8)));
+typedef unsigned int BufU32x4 __attribute__((__vector_size__(16)));
 
 struct PlaneBuf {
   __amdgpu_buffer_rsrc_t r;
@@ -58,6 +59,45 @@ __device__ __forceinline__ void buf_store(float v, PlaneBuf b, uint32_t lane_off
 {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, (int)lane_off,
                                         (int)row_off, 0);
+}
+
+// Two adjacent elements as one access (16 bytes for double, 8 for float).  The hardware
+// needs only 4-byte alignment for these; the pair at an odd element index of a double array
+// is 8-byte aligned.
+__device__ __forceinline__ void buf_load2(PlaneBuf b, uint32_t lane_off, uint32_t row_off,
+                                          double& a0, double& a1)
+{
+  const BufU32x4 v = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)lane_off, (int)row_off, 0);
+  a0 = __hiloint2double((int)v[1], (int)v[0]);
+  a1 = __hiloint2double((int)v[3], (int)v[2]);
+}
+
+__device__ __forceinline__ void buf_load2(PlaneBuf b, uint32_t lane_off, uint32_t row_off,
+                                          float& a0, float& a1)
+{
+  const BufU32x2 v = __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)lane_off, (int)row_off, 0);
+  a0 = __uint_as_float(v[0]);
+  a1 = __uint_as_float(v[1]);
+}
+
+__device__ __forceinline__ void buf_store2(double a0, double a1, PlaneBuf b, uint32_t lane_off,
+                                           uint32_t row_off)
+{
+  BufU32x4 v;
+  v[0] = (unsigned)__double2loint(a0);
+  v[1] = (unsigned)__double2hiint(a0);
+  v[2] = (unsigned)__double2loint(a1);
+  v[3] = (unsigned)__double2hiint(a1);
+  __builtin_amdgcn_raw_buffer_store_b128(v, b.r, (int)lane_off, (int)row_off, 0);
+}
+
+__device__ __forceinline__ void buf_store2(float a0, float a1, PlaneBuf b, uint32_t lane_off,
+                                           uint32_t row_off)
+{
+  BufU32x2 v;
+  v[0] = __float_as_uint(a0);
+  v[1] = __float_as_uint(a1);
+  __builtin_amdgcn_raw_buffer_store_b64(v, b.r, (int)lane_off, (int)row_off, 0);
 }
 
 }  // namespace mgk

@@ -389,6 +389,343 @@ struct Stream {
   }
 };
 
+// Norm and refinement passes with an exact partition of the interior (no tile overlap).
+//
+// A workgroup of W waves owns the interior nodes of a tile of BX = 128*CP columns x
+// BY = W*RPW rows of a z-chunk.  Lane l of wave w holds the column pairs (c, c+1) with
+// c = ox + 128p + 2l, p < CP, of the rows oy + w*RPW + i; the tile origin ox is odd, so
+// each pair is one 16-byte access (8 bytes in the FP32 arrays), and the last interior
+// column n-2 (odd, n = 2^m + 1) opens the pair whose second column is the boundary n-1.
+// The one-node halo is loaded, not recomputed: the column left and right of the tile by
+// lanes 0 and 63 of one extra load per row, the row below / above the tile by the first /
+// last wave.  x-neighbours come from adjacent lanes by DPP (the lane without a source lane
+// takes the halo column or the adjacent pair's edge lane instead of 0), y-neighbours from
+// the lane's own rows or the adjacent wave's edge rows through LDS (double-buffered, one
+// barrier per plane), z-neighbours from a queue of three planes.  Compared with
+// overlapping 128-column tiles this drops the tiles that own a few columns at the end of
+// a row and halves the memory instructions.
+template <bool VAR, int MODE, int W, int RPW, int CP>
+struct Pass {
+  static_assert(W >= 2, "the first and the last wave load the tile's halo rows");
+  static constexpr int BX = 128 * CP, BY = W * RPW;
+  static constexpr int NE = RPW > 1 ? 2 : 1;  // edge rows of a wave: first, last
+
+  struct Shared {
+    double eu[2][W][NE][CP][2][64];  // [buffer][wave][first/last row][pair][column][lane]
+    double ek[VAR ? 2 : 1][VAR ? W : 1][VAR ? NE : 1][VAR ? CP : 1][2][64];
+    double red[W];
+  };
+
+  struct Args {
+    const double* f;
+    const double* u;
+    const double* k;
+    double* out;         // refinement: u_out
+    const float* e;      // refinement: correction (nullptr: none)
+    float* r32;          // refinement: scaled residual
+    double* partial;
+    double scale;        // refinement: u_out = u + scale * e
+    double inv_scale;    // refinement: r32 = r * inv_scale
+    int zero_interior;   // norm: read the interior of u as 0
+    int n;
+    double ih2;
+    int tiles_x, tiles_y, zlen;
+  };
+
+  __device__ __forceinline__ static void run(const Args& a, Shared& sh)
+  {
+    const int n = a.n;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-aware tile index (workgroup b runs on XCD b % 8): the y-adjacent tiles of a
+    // z-chunk, which share their halo rows, run on one XCD and its L2
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int xcd = b & 7, jb = b >> 3, q = nb >> 3, rem = nb & 7;
+    const int t = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + jb;
+    const int tx = t % a.tiles_x, ty = (t / a.tiles_x) % a.tiles_y, tz = t / (a.tiles_x * a.tiles_y);
+    const int ox = 1 + tx * BX, oy = 1 + ty * BY;
+    const int z0 = 1 + tz * a.zlen, z1 = min(z0 + a.zlen, n - 1);  // owned planes [z0, z1)
+
+    // Column pairs: byte offsets (double and float arrays); store offsets outside the
+    // plane's range for lanes that own no column of the pair (those stores are dropped).
+    uint32_t cb[CP], cf[CP], sb[CP], sf[CP];
+    bool in0[CP], in1[CP];
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const int c = ox + 128 * p + 2 * lane;
+      const uint32_t lc = (uint32_t)min(c, n - 2);
+      in0[p] = c <= n - 2;
+      in1[p] = c + 1 <= n - 2;
+      cb[p] = lc * 8u;
+      cf[p] = lc * 4u;
+      sb[p] = in0[p] ? cb[p] : 0x80000000u;
+      sf[p] = in0[p] ? cf[p] : 0x80000000u;
+    }
+    const int hc = lane == 63 ? min(ox + BX, n - 1) : ox - 1;  // halo column (lanes 0, 63)
+    const bool hcin = hc >= 1 && hc <= n - 2;
+    const uint32_t hcb = (uint32_t)hc * 8u, hcf = (uint32_t)hc * 4u;
+    uint32_t rb8[RPW], rb4[RPW];
+    bool rin[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int gy = oy + w * RPW + i;
+      const uint32_t r = (uint32_t)(min(gy, n - 1) * n);
+      rb8[i] = r * 8u;
+      rb4[i] = r * 4u;
+      rin[i] = gy <= n - 2;
+    }
+    const bool hw = w == 0 || w == W - 1;  // loads a halo row
+    const int hy = w == 0 ? oy - 1 : min(oy + BY, n - 1);
+    const bool hyin = hy >= 1 && hy <= n - 2;
+    const uint32_t hrb8 = (uint32_t)(hy * n) * 8u, hrb4 = (uint32_t)(hy * n) * 4u;
+    const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * 8u);
+    const uint32_t planef = (uint32_t)((size_t)n * (size_t)n * 4u);
+    const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;
+    const bool corr = MODE == kRefine && a.e != nullptr;
+
+    // Norm with zero_interior reads interior values of u as 0; the refinement pass adds
+    // scale * e to them.
+    auto adjust = [&](double v, float ev, bool in) -> double {
+      if constexpr (MODE == kNorm) return (a.zero_interior && in) ? 0.0 : v;
+      else return (corr && in) ? v + a.scale * (double)ev : v;
+    };
+
+    // Queue of the planes s-1, s, s+1 (u adjusted; k); plane s+2 in flight.  f, the halo
+    // column and the halo row are needed on plane s only: plane s+1 in flight.
+    double U[3][RPW][CP][2], K[VAR ? 3 : 1][RPW][CP][2];
+    double PU[RPW][CP][2], PK[RPW][CP][2];
+    float PE[RPW][CP][2];
+    double F[RPW][CP][2], PF[RPW][CP][2];
+    double X[RPW], PX[RPW], XK[RPW], PXK[RPW];
+    float PXE[RPW];
+    double H[CP][2], PH[CP][2], HK[CP][2], PHK[CP][2];
+    float PHE[CP][2];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      PXE[i] = 0.0f;
+#pragma unroll
+      for (int p = 0; p < CP; ++p) PE[i][p][0] = PE[i][p][1] = 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < CP; ++p) PHE[p][0] = PHE[p][1] = 0.0f;
+
+    auto load_q = [&](int z) {
+      const size_t zc = (size_t)min(max(z, 0), n - 1);
+      const PlaneBuf bu = plane_buf(a.u, zc * planeb, planeb);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int p = 0; p < CP; ++p) buf_load2(bu, cb[p], rb8[i], PU[i][p][0], PU[i][p][1]);
+      if constexpr (VAR) {
+        const PlaneBuf bk = plane_buf(a.k, zc * planeb, planeb);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+          for (int p = 0; p < CP; ++p) buf_load2(bk, cb[p], rb8[i], PK[i][p][0], PK[i][p][1]);
+      }
+      if (corr) {
+        const PlaneBuf be = plane_buf(a.e, zc * planef, planef);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+          for (int p = 0; p < CP; ++p) buf_load2(be, cf[p], rb4[i], PE[i][p][0], PE[i][p][1]);
+      }
+    };
+    auto shift_in = [&](int z) {
+      const bool zin = z >= 1 && z <= n - 2;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int p = 0; p < CP; ++p)
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const double v = adjust(PU[i][p][o], PE[i][p][o], zin && rin[i] && (o ? in1[p] : in0[p]));
+            U[0][i][p][o] = U[1][i][p][o]; U[1][i][p][o] = U[2][i][p][o]; U[2][i][p][o] = v;
+            if constexpr (VAR) {
+              K[0][i][p][o] = K[1][i][p][o]; K[1][i][p][o] = K[2][i][p][o]; K[2][i][p][o] = PK[i][p][o];
+            }
+          }
+    };
+    auto load_c = [&](int z) {
+      const size_t zc = (size_t)min(max(z, 0), n - 1);
+      const PlaneBuf bu = plane_buf(a.u, zc * planeb, planeb);
+      const PlaneBuf bf = plane_buf(a.f, zc * planeb, planeb);
+      const PlaneBuf bk = plane_buf(a.k, zc * planeb, planeb);
+      const PlaneBuf be = plane_buf(a.e, zc * planef, planef);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+#pragma unroll
+        for (int p = 0; p < CP; ++p) buf_load2(bf, cb[p], rb8[i], PF[i][p][0], PF[i][p][1]);
+        PX[i] = buf_load<double>(bu, hcb, rb8[i]);
+        if constexpr (VAR) PXK[i] = buf_load<double>(bk, hcb, rb8[i]);
+        if (corr) PXE[i] = buf_load<float>(be, hcf, rb4[i]);
+      }
+      if (hw) {
+#pragma unroll
+        for (int p = 0; p < CP; ++p) {
+          buf_load2(bu, cb[p], hrb8, PH[p][0], PH[p][1]);
+          if constexpr (VAR) buf_load2(bk, cb[p], hrb8, PHK[p][0], PHK[p][1]);
+          if (corr) buf_load2(be, cf[p], hrb4, PHE[p][0], PHE[p][1]);
+        }
+      }
+    };
+    auto take_c = [&](int z) {
+      const bool zin = z >= 1 && z <= n - 2;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+#pragma unroll
+        for (int p = 0; p < CP; ++p) {
+          F[i][p][0] = PF[i][p][0];
+          F[i][p][1] = PF[i][p][1];
+        }
+        X[i] = adjust(PX[i], PXE[i], zin && rin[i] && hcin);
+        if constexpr (VAR) XK[i] = PXK[i];
+      }
+#pragma unroll
+      for (int p = 0; p < CP; ++p)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          H[p][o] = adjust(PH[p][o], PHE[p][o], zin && hyin && (o ? in1[p] : in0[p]));
+          if constexpr (VAR) HK[p][o] = PHK[p][o];
+        }
+    };
+    auto write_edges = [&](int buf, int slot) {
+#pragma unroll
+      for (int p = 0; p < CP; ++p)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          sh.eu[buf][w][0][p][o][lane] = U[slot][0][p][o];
+          if constexpr (NE == 2) sh.eu[buf][w][1][p][o][lane] = U[slot][RPW - 1][p][o];
+          if constexpr (VAR) {
+            sh.ek[buf][w][0][p][o][lane] = K[slot][0][p][o];
+            if constexpr (NE == 2) sh.ek[buf][w][1][p][o][lane] = K[slot][RPW - 1][p][o];
+          }
+        }
+    };
+
+    float RK[RPW][CP][2];
+    double sumsq = 0.0;
+    auto store = [&](int sp) {  // u_out from queue slot 0, r32 from RK
+      const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
+      const PlaneBuf br = plane_buf(a.r32, (size_t)sp * planef, planef);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        if (!rin[i]) continue;
+#pragma unroll
+        for (int p = 0; p < CP; ++p) {
+          buf_store2(U[0][i][p][0], U[0][i][p][1], bo, sb[p], rb8[i]);
+          buf_store2(RK[i][p][0], RK[i][p][1], br, sf[p], rb4[i]);
+        }
+      }
+    };
+
+    // prologue: planes z0-1, z0, z0+1 queued, the plane arrays of z0 taken, the edges of
+    // plane z0 written for the first step
+    load_q(z0 - 1);
+    shift_in(z0 - 1);
+    load_q(z0);
+    shift_in(z0);
+    load_q(z0 + 1);
+    shift_in(z0 + 1);
+    load_c(z0);
+    take_c(z0);
+    write_edges(1, 1);
+
+    auto stepfn = [&](auto BC, int s) {
+      constexpr int bb = decltype(BC)::value;
+      constexpr int rb = 1 - bb, wb = bb;  // LDS buffer written in the previous / this step
+      __syncthreads();
+      if (MODE == kRefine && s > z0) store(s - 1);
+      if (s + 2 <= z1) load_q(s + 2);
+      if (s + 1 < z1) load_c(s + 1);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+#pragma unroll
+        for (int p = 0; p < CP; ++p) {
+          // x-neighbours: the lane without a source lane takes the adjacent pair's edge lane
+          // or, at the tile's edge, the halo column (lane 0 left, lane 63 right)
+          const double fl = p == 0 ? X[i] : lane_value(U[1][i][p - 1][1], 63);
+          const double fr = p == CP - 1 ? X[i] : lane_value(U[1][i][p + 1][0], 0);
+          const double l1 = from_lane_below_or(U[1][i][p][1], fl);
+          const double r0 = from_lane_above_or(U[1][i][p][0], fr);
+          double kl1 = 0.0, kr0 = 0.0;
+          if constexpr (VAR) {
+            const double gl = p == 0 ? XK[i] : lane_value(K[1][i][p - 1][1], 63);
+            const double gr = p == CP - 1 ? XK[i] : lane_value(K[1][i][p + 1][0], 0);
+            kl1 = from_lane_below_or(K[1][i][p][1], gl);
+            kr0 = from_lane_above_or(K[1][i][p][0], gr);
+          }
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const double ui = U[1][i][p][o];
+            const double xm = o == 0 ? l1 : U[1][i][p][0];
+            const double xp = o == 0 ? U[1][i][p][1] : r0;
+            double ym, yp, kym = 0.0, kyp = 0.0;
+            if (i > 0) {
+              ym = U[1][i - 1][p][o];
+              if constexpr (VAR) kym = K[1][i - 1][p][o];
+            } else {
+              ym = w > 0 ? sh.eu[rb][wm][NE - 1][p][o][lane] : H[p][o];
+              if constexpr (VAR) kym = w > 0 ? sh.ek[rb][wm][NE - 1][p][o][lane] : HK[p][o];
+            }
+            if (i < RPW - 1) {
+              yp = U[1][i + 1][p][o];
+              if constexpr (VAR) kyp = K[1][i + 1][p][o];
+            } else {
+              yp = w < W - 1 ? sh.eu[rb][wp][0][p][o][lane] : H[p][o];
+              if constexpr (VAR) kyp = w < W - 1 ? sh.ek[rb][wp][0][p][o][lane] : HK[p][o];
+            }
+            const double zm = U[0][i][p][o], zp = U[2][i][p][o];
+            double au;
+            if constexpr (!VAR) {
+              au = au_const<double, 3>(a.ih2, ui, xm, xp, ym, yp, zm, zp);
+            } else {
+              const double kxm = o == 0 ? kl1 : K[1][i][p][0];
+              const double kxp = o == 0 ? K[1][i][p][1] : kr0;
+              au = au_var<double, 3>(a.ih2, ui, K[1][i][p][o], xm, kxm, xp, kxp, ym, kym, yp,
+                                     kyp, zm, K[0][i][p][o], zp, K[2][i][p][o]);
+            }
+            const double r = F[i][p][o] - au;
+            const bool own = rin[i] && (o ? in1[p] : in0[p]);
+            if (own) sumsq += r * r;
+            if constexpr (MODE == kRefine) RK[i][p][o] = own ? (float)(r * a.inv_scale) : 0.0f;
+          }
+        }
+      }
+      write_edges(wb, 2);  // edges of plane s+1
+      shift_in(s + 2);
+      if (s + 1 < z1) take_c(s + 1);
+    };
+
+    for (int s = z0; s < z1;) {
+      stepfn(IC<0>{}, s);
+      if (++s >= z1) break;
+      stepfn(IC<1>{}, s);
+      ++s;
+    }
+    if (MODE == kRefine) store(z1 - 1);  // queue slot 0 holds plane z1-1
+
+#pragma unroll
+    for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
+    __syncthreads();
+    if (lane == 0) sh.red[w] = sumsq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int v = 0; v < W; ++v) tot += sh.red[v];
+      a.partial[blockIdx.x] = tot;
+    }
+  }
+};
+
+template <bool VAR, int MODE, int W, int RPW, int CP>
+__global__ void __launch_bounds__(64 * W) k_pass(typename Pass<VAR, MODE, W, RPW, CP>::Args a)
+{
+  using C = Pass<VAR, MODE, W, RPW, CP>;
+  __shared__ typename C::Shared sh;
+  C::run(a, sh);
+}
+
 template <typename T, bool VAR, int MODE, int W, int RPW, int PD>
 __global__ void __launch_bounds__(64 * W) k_stream(typename Stream<T, VAR, MODE, W, RPW, PD>::Args a)
 {
@@ -509,15 +846,36 @@ void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const 
 }
 
 namespace {
-template <bool VAR, int MODE, int W, int RPW>
-void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, W, RPW, 2>::Args a, double* partial,
+// Shapes of the exact-partition passes (waves x rows per wave x column pairs per lane),
+// from timing sweeps on MI355X at 513^3.
+#ifndef MG_PASS_W
+#define MG_PASS_W 8
+#endif
+#ifndef MG_PASS_RPW
+#define MG_PASS_RPW 2
+#endif
+#ifndef MG_PASS_CP
+#define MG_PASS_CP 2
+#endif
+#ifndef MG_PASS_VAR_W
+#define MG_PASS_VAR_W 8
+#endif
+#ifndef MG_PASS_VAR_RPW
+#define MG_PASS_VAR_RPW 1
+#endif
+#ifndef MG_PASS_VAR_CP
+#define MG_PASS_VAR_CP 2
+#endif
+
+template <bool VAR, int MODE, int W, int RPW, int CP>
+void launch_pass(hipStream_t s, typename Pass<VAR, MODE, W, RPW, CP>::Args a, double* partial,
                  double* out)
 {
-  using C = Stream<double, VAR, MODE, W, RPW, 2>;
-  auto kern = k_stream<double, VAR, MODE, W, RPW, 2>;
+  using C = Pass<VAR, MODE, W, RPW, CP>;
+  auto kern = k_pass<VAR, MODE, W, RPW, CP>;
   const int m = a.n - 2;
-  a.tiles_x = (m + C::OX - 1) / C::OX;
-  a.tiles_y = (m + C::OY - 1) / C::OY;
+  a.tiles_x = (m + C::BX - 1) / C::BX;
+  a.tiles_y = (m + C::BY - 1) / C::BY;
   const int per = a.tiles_x * a.tiles_y;
   a.zlen = best_zlen(per, m, 2, capacity_of(kern, 64 * W), kStreamPartials);
   const int blocks = per * ((m + a.zlen - 1) / a.zlen);
@@ -525,19 +883,39 @@ void launch_fine(hipStream_t s, typename Stream<double, VAR, MODE, W, RPW, 2>::A
   kern<<<blocks, 64 * W, 0, s>>>(a);
   k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
 }
+
+template <bool VAR, int MODE>
+void run_pass(hipStream_t s, typename Pass<VAR, MODE, 4, 2, 4>::Args a, double* partial,
+              double* out)
+{
+  // Args does not depend on the shape
+  constexpr int W = VAR ? MG_PASS_VAR_W : MG_PASS_W, RPW = VAR ? MG_PASS_VAR_RPW : MG_PASS_RPW;
+  constexpr int CP = VAR ? MG_PASS_VAR_CP : MG_PASS_CP, CPS = CP < 2 ? CP : 2;
+  using A = typename Pass<VAR, MODE, W, RPW, CP>::Args;
+  using AS = typename Pass<VAR, MODE, W, RPW, CPS>::Args;
+  static_assert(sizeof(A) == sizeof(a) && sizeof(AS) == sizeof(a), "argument layout");
+  // a 256-column tile covers the interior row of n = 257
+  if (a.n - 2 > 128 * CPS)
+    launch_pass<VAR, MODE, W, RPW, CP>(s, __builtin_bit_cast(A, a), partial, out);
+  else
+    launch_pass<VAR, MODE, W, RPW, CPS>(s, __builtin_bit_cast(AS, a), partial, out);
+}
 }  // namespace
 
 void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
                        const double* u, int mode, double* partial, double* out)
 {
+  auto fill = [&](auto& a) {
+    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
+  };
   if (k) {
-    Stream<double, true, kNorm, kNW, kNRPW, 2>::Args a{};
-    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
-    launch_fine<true, kNorm, kNW, kNRPW>(s, a, partial, out);
+    Pass<true, kNorm, 4, 2, 4>::Args a{};
+    fill(a);
+    run_pass<true, kNorm>(s, a, partial, out);
   } else {
-    Stream<double, false, kNorm, kNW, kNRPW, 2>::Args a{};
-    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.zero_interior = mode;
-    launch_fine<false, kNorm, kNW, kNRPW>(s, a, partial, out);
+    Pass<false, kNorm, 4, 2, 4>::Args a{};
+    fill(a);
+    run_pass<false, kNorm>(s, a, partial, out);
   }
 }
 
@@ -545,16 +923,18 @@ void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double
                    const double* u, const float* e, double scale, double inv_scale, double* uout,
                    float* r32, double* partial, double* out)
 {
+  auto fill = [&](auto& a) {
+    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
+    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
+  };
   if (k) {
-    Stream<double, true, kRefine, kRVW, kRRPW, 2>::Args a{};
-    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
-    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
-    launch_fine<true, kRefine, kRVW, kRRPW>(s, a, partial, out);
+    Pass<true, kRefine, 4, 2, 4>::Args a{};
+    fill(a);
+    run_pass<true, kRefine>(s, a, partial, out);
   } else {
-    Stream<double, false, kRefine, kRW, kRRPW, 2>::Args a{};
-    a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
-    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
-    launch_fine<false, kRefine, kRW, kRRPW>(s, a, partial, out);
+    Pass<false, kRefine, 4, 2, 4>::Args a{};
+    fill(a);
+    run_pass<false, kRefine>(s, a, partial, out);
   }
 }
 
