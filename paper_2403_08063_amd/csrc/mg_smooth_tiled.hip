@@ -644,9 +644,13 @@ void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T*
 
 }  // namespace
 
-// The per-colour kernel is faster up to 129^3 (a 3D level that small streams too few
-// planes per workgroup to hide the pipeline's start-up).
-bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n > 129; }
+// The per-colour kernel is faster up to 65^3 (a 3D level that small streams too few
+// planes per workgroup to hide the pipeline's start-up); from 129^3 on, the two launches
+// per level and cycle of the fused kernels beat the ten of the per-colour path.
+#ifndef MG_TILED_MIN_N
+#define MG_TILED_MIN_N 65
+#endif
+bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n > MG_TILED_MIN_N; }
 
 bool rbgs_tiled_fuses_prolong(size_t value_bytes)
 {

@@ -14,7 +14,8 @@ import pytest
 import torch
 
 from conftest import interior, relmax
-from paper_2403_08063_amd import FUSE_ALL, FUSE_PROLONG, FUSE_RESTRICT, FUSE_ZERO, Multigrid, inputs
+from paper_2403_08063_amd import (FUSE_ALL, FUSE_PROLONG, FUSE_RESTRICT, FUSE_TAIL, FUSE_ZERO,
+                                  Multigrid, inputs)
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +48,8 @@ def say(*a):
 
 
 # ---------------------------------------------------------------- single steps
-# the temporally blocked smoother and the streaming residual kernels serve 3D levels
-# above 129^3: 161 and 257 exercise them with ragged last tiles
+# the temporally blocked smoother serves 3D levels from 129^3 on, the streaming residual
+# kernels the fine level from there: 161 and 257 exercise them with ragged last tiles
 SMOOTH_CASES = [  # dim, n, levels, variable
     (2, 129, 6, False), (2, 65, 5, True), (3, 17, 3, False), (3, 65, 5, False),
     (3, 129, 6, False), (3, 65, 5, True), (3, 161, 6, False), (3, 161, 6, True),
@@ -73,7 +74,8 @@ def test_smooth_matches_oracle(oracle, dim, n, levels, var, sweeps):
     assert relmax(host(ug), uo) <= 1e-14
 
 
-@pytest.mark.parametrize("n,var", [(161, False), (257, False), (161, True), (257, True)])
+@pytest.mark.parametrize("n,var", [(129, False), (129, True), (161, False), (257, False), (161, True),
+                                   (257, True)])
 def test_blocked_smoother_bitwise_equals_per_colour(n, var):
     """The temporally blocked out-of-place smoother and the per-colour in-place kernel give
     bitwise-identical iterates (same formulas, exact red-black order)."""
@@ -83,7 +85,7 @@ def test_blocked_smoother_bitwise_equals_per_colour(n, var):
     u0 = random_interior(3, n, 6)
     out = []
     for fused in (True, False):
-        mg = Multigrid(3, n, 6 if n == 161 else 7, variable=var, device=DEV)
+        mg = Multigrid(3, n, {129: 6, 161: 6}.get(n, 7), variable=var, device=DEV)
         mg.set_fusion(fused)
         if var:
             mg.set_coefficients(dev(k))
@@ -97,15 +99,15 @@ def test_blocked_smoother_bitwise_equals_per_colour(n, var):
                                                     (3, 129, 7, True, "f64"), (3, 65, 6, False, "f32_ir"),
                                                     (3, 65, 5, True, "f32_ir"), (2, 65, 5, True, "f64")])
 def test_coarse_tail_bitwise_equals_per_level_launches(dim, n, levels, var, prec):
-    """The one-launch coarse tail reproduces the per-level launches bit for bit (levels up to
-    129^3 use no streaming kernels, so the whole cycle must agree exactly)."""
+    """The one-launch coarse tail reproduces the per-level launches bit for bit (only the
+    tail is switched off; every other level runs the same kernels in both cycles)."""
     say(f"coarse tail dim={dim} n={n} var={var} prec={prec}")
     k = random_k(dim, n, 24) if var else None
     f = dev(inputs.uniform_interior(dim, n, 25))
     out = []
-    for fused in (True, False):
+    for flags in (FUSE_ALL, FUSE_ALL & ~FUSE_TAIL):
         mg = Multigrid(dim, n, levels, variable=var, precision=prec, device=DEV)
-        mg.set_fusion(fused)
+        mg.set_fusion(flags)
         if var:
             mg.set_coefficients(dev(k))
         u = mg.zeros()
