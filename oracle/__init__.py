@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mg_oracle.c")
 _INC = os.path.join(_HERE, "level_ops.inc")
+_FV = os.path.join(_HERE, "fv_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 4: "not converged", 5: "non-finite norm"}
@@ -27,12 +28,12 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 4: "not converged"
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain C + OpenMP, no fused multiply-add)."""
-    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_INC))
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_INC), os.path.getmtime(_FV))
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= newest:
         return _LIB
     tmp = _LIB + f".tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+           "-fno-fast-math", "-Wall", "-o", tmp, _SRC, _FV, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
     os.replace(tmp, _LIB)
     return _LIB
@@ -64,6 +65,15 @@ def lib() -> ctypes.CDLL:
             "or_vcycle": (i, [i, i, i, i, i, P, P, P]),
             "or_solve": (i, [i, i, i, i, i, i, i, P, P, P, d, P, P, P]),
             "or_grad": (None, [i, i, P, P, P, P]),
+            "or_fv_apply": (None, [i, d, P, P]),
+            "or_fv_residual": (None, [i, d, P, P, P]),
+            "or_fv_jacobi": (None, [i, d, d, P, P, P]),
+            "or_fv_jacobi_sweeps": (i, [i, d, d, P, P, i]),
+            "or_fv_restrict": (None, [i, P, P]),
+            "or_fv_prolong_add": (None, [i, P, P]),
+            "or_fv_norm2": (d, [i, P]),
+            "or_fv_vcycle": (i, [i, i, i, i, i, d, P, P]),
+            "or_fv_solve": (i, [i, i, i, i, i, d, P, P, d, i, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -230,3 +240,94 @@ def grad(u, lam):
     df = np.empty_like(u)
     lib().or_grad(dim, n, _p(_chk(u, dim, n)), _p(_chk(lam, dim, n)), _p(dk), _p(df))
     return dk, df
+
+
+# ------------------------------------------------------------------ cell-centred FV scheme
+# The paper's own benchmark solver on a uniform grid (fv_oracle.c): N^3 cells stored with a
+# one-cell ghost layer, (N+2)^3 values, C order; the ghost layer holds the Dirichlet value at
+# the adjacent face centre.
+FV_OMEGA = 0.8
+
+
+def _fv_n(a):
+    if a.ndim != 3 or len(set(a.shape)) != 1 or a.shape[0] < 4:
+        raise ValueError("FV arrays are (N+2)^3")
+    return a.shape[0] - 2
+
+
+def _fv_chk(a, N, name="array"):
+    if a.dtype != np.float64 or not a.flags.c_contiguous or a.shape != (N + 2,) * 3:
+        raise ValueError(f"{name}: need a C-contiguous float64 array of shape {(N + 2,) * 3}")
+    return a
+
+
+def fv_apply(u, h=None):
+    """A u on the interior cells, 0 on the ghost layer (h defaults to 1/N)."""
+    N = _fv_n(u)
+    out = np.empty_like(u)
+    lib().or_fv_apply(N, 1.0 / N if h is None else h, _p(_fv_chk(u, N)), _p(out))
+    return out
+
+
+def fv_residual(f, u, h=None):
+    N = _fv_n(u)
+    r = np.empty_like(u)
+    lib().or_fv_residual(N, 1.0 / N if h is None else h, _p(_fv_chk(f, N, "f")),
+                         _p(_fv_chk(u, N)), _p(r))
+    return r
+
+
+def fv_jacobi(f, u, h=None, omega=FV_OMEGA, sweeps=1):
+    """Damped Jacobi sweeps; returns the new iterate (u is not modified)."""
+    N = _fv_n(u)
+    out = np.ascontiguousarray(u.copy())
+    st = lib().or_fv_jacobi_sweeps(N, 1.0 / N if h is None else h, float(omega),
+                                   _p(_fv_chk(f, N, "f")), _p(out), int(sweeps))
+    if st:
+        raise RuntimeError(f"fv_jacobi: {STATUS.get(st, st)}")
+    return out
+
+
+def fv_restrict(r):
+    N = _fv_n(r)
+    fc = np.empty((N // 2 + 2,) * 3)
+    lib().or_fv_restrict(N, _p(_fv_chk(r, N)), _p(fc))
+    return fc
+
+
+def fv_prolong_add(e, u):
+    """In place: u += P e on the fine interior (e: coarse correction, ghost layer ignored)."""
+    Nc = _fv_n(e)
+    lib().or_fv_prolong_add(Nc, _p(_fv_chk(e, Nc, "e")), _p(_fv_chk(u, 2 * Nc)))
+    return u
+
+
+def fv_norm2(v):
+    N = _fv_n(v)
+    return lib().or_fv_norm2(N, _p(_fv_chk(v, N)))
+
+
+def fv_vcycle(f, u, levels, nu1=3, nu2=3, coarse_iters=256, omega=FV_OMEGA):
+    """In place: one V(nu1, nu2)-cycle."""
+    N = _fv_n(u)
+    st = lib().or_fv_vcycle(N, levels, nu1, nu2, coarse_iters, float(omega),
+                            _p(_fv_chk(f, N, "f")), _p(_fv_chk(u, N)))
+    if st:
+        raise RuntimeError(f"fv_vcycle: {STATUS.get(st, st)}")
+    return u
+
+
+def fv_solve(f, u, levels, tol=1e-16, max_cycles=35, nu1=3, nu2=3, coarse_iters=256,
+             omega=FV_OMEGA):
+    """In place: V-cycles until the L2 residual norm is <= tol or max_cycles ran.
+    Returns (cycles, residual norm, history of residual norms, status)."""
+    N = _fv_n(u)
+    cyc = ctypes.c_int(0)
+    rn = ctypes.c_double(0.0)
+    hist = np.full(max_cycles + 1, np.nan)
+    st = lib().or_fv_solve(N, levels, nu1, nu2, coarse_iters, float(omega),
+                           _p(_fv_chk(f, N, "f")), _p(_fv_chk(u, N)), float(tol),
+                           int(max_cycles), ctypes.byref(cyc), ctypes.byref(rn), _p(hist))
+    if st not in (0, 4):
+        raise RuntimeError(f"fv_solve: {STATUS.get(st, st)}")
+    return cyc.value, rn.value, hist[: cyc.value + 1].copy(), st

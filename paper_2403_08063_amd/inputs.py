@@ -68,6 +68,40 @@ def harmonic_dirichlet(n: int) -> np.ndarray:
     return np.multiply.outer(sz, np.multiply.outer(sx, sx))
 
 
+# ---------------------------------------------------------------- cell-centred FV grids
+# N^3 cells stored with a one-cell ghost layer: (N+2)^3 values, C order [z][y][x]; cell i in
+# 1..N has its centre at (i - 1/2)/N, and a ghost cell carries the Dirichlet value at the
+# centre of the boundary face it touches.
+
+def fv_centres(N: int) -> np.ndarray:
+    """Cell-centre coordinate of index 0..N+1 along one axis (the ghost entries hold the face
+    coordinates 0 and 1, where their Dirichlet values are taken)."""
+    c = (np.arange(N + 2) - 0.5) / N
+    c[0], c[-1] = 0.0, 1.0
+    return c
+
+
+def fv_harmonic(N: int):
+    """The paper's benchmark (Sect. 5, Eq. 1-2) on N^3 cells: returns (u0, exact), u0 with
+    the Dirichlet data sin(pi x) sin(pi y) sinh(sqrt2 pi z) in the ghost layer and 0 inside,
+    exact the same function at every cell centre (f = 0)."""
+    c = fv_centres(N)
+    sx = np.sin(np.pi * c)
+    sz = np.sinh(np.sqrt(2.0) * np.pi * c)
+    exact = np.multiply.outer(sz, np.multiply.outer(sx, sx))
+    u0 = exact.copy()
+    u0[1:-1, 1:-1, 1:-1] = 0.0
+    return u0, exact
+
+
+def fv_uniform(N: int, seed: int, amplitude: float = 1.0) -> np.ndarray:
+    """amplitude * U[-1,1] iid on the N^3 cells, 0 in the ghost layer."""
+    rng = np.random.default_rng(seed)
+    a = np.zeros((N + 2,) * 3)
+    a[1:-1, 1:-1, 1:-1] = amplitude * rng.uniform(-1.0, 1.0, size=(N,) * 3)
+    return a
+
+
 def gaussian_random_field(dim: int, n: int, seed: int, corr: float = 0.1,
                           sigma: float = 1.0) -> np.ndarray:
     """Stationary Gaussian field with covariance sigma^2 exp(-r^2 / (2 corr^2)).
