@@ -26,6 +26,10 @@ EXPORTS = [
     "mg_restrict_residual", "mg_restrict_residual_f32", "mg_prolong_correct",
     "mg_prolong_correct_f32", "mg_coarsest_solve", "mg_residual_norm2",
     "mg_set_fusion", "mg_last_error", "mg_destroy",
+    # include/mg_fv.h
+    "mgfv_workspace_bytes", "mgfv_setup", "mgfv_destroy", "mgfv_last_error", "mgfv_jacobi",
+    "mgfv_residual", "mgfv_restrict_residual", "mgfv_prolong_correct", "mgfv_coarse_solve",
+    "mgfv_residual_norm2", "mgfv_vcycle", "mgfv_solve",
 ]
 
 
@@ -33,6 +37,12 @@ class MgGrid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("levels", ctypes.c_int),
                 ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("precision", ctypes.c_int), ("variable", ctypes.c_int)]
+
+
+class MgFvGrid(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("omega", ctypes.c_double),
+                ("max_cycles", ctypes.c_int)]
 
 
 class MgError(RuntimeError):
@@ -55,6 +65,7 @@ def lib() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     i, d, P, S = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     G = ctypes.POINTER(MgGrid)
+    FG = ctypes.POINTER(MgFvGrid)
     PI, PD = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     sig = {
         "mg_validate": (i, [G]),
@@ -77,6 +88,18 @@ def lib() -> ctypes.CDLL:
         "mg_set_fusion": (i, [P, i]),
         "mg_last_error": (ctypes.c_char_p, [P]),
         "mg_destroy": (None, [P]),
+        "mgfv_workspace_bytes": (S, [FG]),
+        "mgfv_setup": (i, [FG, P, S, P, ctypes.POINTER(P)]),
+        "mgfv_destroy": (None, [P]),
+        "mgfv_last_error": (ctypes.c_char_p, [P]),
+        "mgfv_jacobi": (i, [P, i, P, P, i]),
+        "mgfv_residual": (i, [P, i, P, P, P]),
+        "mgfv_restrict_residual": (i, [P, i, P, P, P]),
+        "mgfv_prolong_correct": (i, [P, i, P, P]),
+        "mgfv_coarse_solve": (i, [P, P, P]),
+        "mgfv_residual_norm2": (i, [P, P, P, PD]),
+        "mgfv_vcycle": (i, [P, P, P]),
+        "mgfv_solve": (i, [P, P, P, d, PI, PD]),
     }
     for name in EXPORTS:
         res, args = sig[name]
@@ -95,4 +118,12 @@ def last_error(ctx=None) -> str:
 def check(status: int, ctx=None, allow=()) -> int:
     if status != MG_OK and status not in allow:
         raise MgError(status, last_error(ctx))
+    return status
+
+
+def check_fv(status: int, ctx=None, allow=()) -> int:
+    """check() for the finite-volume contexts (their own error text)."""
+    if status != MG_OK and status not in allow:
+        msg = lib().mgfv_last_error(ctx)
+        raise MgError(status, msg.decode() if msg else "")
     return status

@@ -126,4 +126,16 @@ void copy_boundary(hipStream_t s, int dim, int n, const double* src, double* dst
 // Sets the boundary nodes of p to 0.
 void zero_boundary(hipStream_t s, int dim, int n, double* p);
 
+// ---- cell-centred finite volumes (N^3 cells, arrays of (N+2)^3 values with a ghost layer
+// holding the Dirichlet value at the adjacent face centre; a ghost neighbour enters the
+// 7-point operator as 2 g - u_i).
+// Exact-partition streaming passes for N >= 128 (mg_resid_tiled.hip):
+bool fv_tiled_supported(int N);
+// one damped Jacobi sweep, uout = u + omega h^2/6 (f - A u) on the cells (ghosts untouched)
+void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double* f,
+                     const double* u, double* uout, double* partial);
+// out = sum over cells of (f - A u)^2 (partial: kStreamPartials doubles)
+void fv_norm2_tiled(hipStream_t s, int N, double h, const double* f, const double* u,
+                    double* partial, double* out);
+
 }  // namespace mgk

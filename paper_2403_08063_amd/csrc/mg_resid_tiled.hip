@@ -35,7 +35,21 @@ namespace {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-enum { kRestrict = 0, kNorm = 1, kRefine = 2 };
+enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4 };
+
+// (A u)_i of the cell-centred finite-volume operator from the six neighbour values (ghost
+// neighbours already replaced by 2 g - u_i), in the order -x, +x, -y, +y, -z, +z.
+__device__ __forceinline__ double fv_au(double ih2, double ui, double v0, double v1, double v2,
+                                        double v3, double v4, double v5)
+{
+  double s = ui - v0;
+  s = s + (ui - v1);
+  s = s + (ui - v2);
+  s = s + (ui - v3);
+  s = s + (ui - v4);
+  s = s + (ui - v5);
+  return s * ih2;
+}
 
 template <typename T, bool VAR, int MODE, int W, int RPW, int PD>
 struct Stream {
@@ -404,8 +418,15 @@ struct Stream {
 // barrier per plane), z-neighbours from a queue of three planes.  Compared with
 // overlapping 128-column tiles this drops the tiles that own a few columns at the end of
 // a row and halves the memory instructions.
+//
+// The same decomposition serves the cell-centred finite-volume scheme (MODE kFvNorm,
+// kFvJacobi): N^3 cells with a ghost layer, n = N + 2 values per side.  The ghost layer
+// holds the Dirichlet value at the face centre, and a ghost neighbour enters the operator
+// as 2 g - u_i; kFvJacobi writes the damped Jacobi update u + coef (f - A u) out of place.
 template <bool VAR, int MODE, int W, int RPW, int CP>
 struct Pass {
+  static constexpr bool FV = MODE == kFvNorm || MODE == kFvJacobi;
+  static_assert(!(FV && VAR), "the finite-volume scheme has a constant coefficient");
   static_assert(W >= 2, "the first and the last wave load the tile's halo rows");
   static constexpr int BX = 128 * CP, BY = W * RPW;
   static constexpr int NE = RPW > 1 ? 2 : 1;  // edge rows of a wave: first, last
@@ -426,6 +447,7 @@ struct Pass {
     double* partial;
     double scale;        // refinement: u_out = u + scale * e
     double inv_scale;    // refinement: r32 = r * inv_scale
+    double coef;         // finite-volume Jacobi: u_out = u + coef * (f - A u)
     int zero_interior;   // norm: read the interior of u as 0
     int n;
     double ih2;
@@ -482,11 +504,28 @@ struct Pass {
     const uint32_t planef = (uint32_t)((size_t)n * (size_t)n * 4u);
     const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;
     const bool corr = MODE == kRefine && a.e != nullptr;
+    // finite volumes: which neighbours of a lane's cells are ghost cells (x per pair and
+    // column, y per row; z per plane in the step)
+    bool gx0[CP], gxp0[CP], gxp1[CP], gym[RPW], gyp[RPW];
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const int c = ox + 128 * p + 2 * lane;
+      gx0[p] = c == 1;
+      gxp0[p] = c + 1 == n - 1;
+      gxp1[p] = c + 2 == n - 1;
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int gy = oy + w * RPW + i;
+      gym[i] = gy == 1;
+      gyp[i] = gy + 1 == n - 1;
+    }
 
     // Norm with zero_interior reads interior values of u as 0; the refinement pass adds
     // scale * e to them.
     auto adjust = [&](double v, float ev, bool in) -> double {
-      if constexpr (MODE == kNorm) return (a.zero_interior && in) ? 0.0 : v;
+      if constexpr (FV) return v;
+      else if constexpr (MODE == kNorm) return (a.zero_interior && in) ? 0.0 : v;
       else return (corr && in) ? v + a.scale * (double)ev : v;
     };
 
@@ -604,9 +643,19 @@ struct Pass {
     };
 
     float RK[RPW][CP][2];
+    double JV[MODE == kFvJacobi ? RPW : 1][CP][2];
     double sumsq = 0.0;
     auto store = [&](int sp) {  // u_out from queue slot 0, r32 from RK
       const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
+      if constexpr (MODE == kFvJacobi) {
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          if (!rin[i]) continue;
+#pragma unroll
+          for (int p = 0; p < CP; ++p) buf_store2(JV[i][p][0], JV[i][p][1], bo, sb[p], rb8[i]);
+        }
+        return;
+      }
       const PlaneBuf br = plane_buf(a.r32, (size_t)sp * planef, planef);
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
@@ -635,7 +684,8 @@ struct Pass {
       constexpr int bb = decltype(BC)::value;
       constexpr int rb = 1 - bb, wb = bb;  // LDS buffer written in the previous / this step
       __syncthreads();
-      if (MODE == kRefine && s > z0) store(s - 1);
+      if ((MODE == kRefine || MODE == kFvJacobi) && s > z0) store(s - 1);
+      const bool gzm = s == 1, gzp = s + 1 == n - 1;
       if (s + 2 <= z1) load_q(s + 2);
       if (s + 1 < z1) load_c(s + 1);
 #pragma unroll
@@ -677,7 +727,12 @@ struct Pass {
             }
             const double zm = U[0][i][p][o], zp = U[2][i][p][o];
             double au;
-            if constexpr (!VAR) {
+            if constexpr (FV) {
+              const bool gxm = o == 0 && gx0[p], gxp = o == 0 ? gxp0[p] : gxp1[p];
+              au = fv_au(a.ih2, ui, gxm ? 2.0 * xm - ui : xm, gxp ? 2.0 * xp - ui : xp,
+                         gym[i] ? 2.0 * ym - ui : ym, gyp[i] ? 2.0 * yp - ui : yp,
+                         gzm ? 2.0 * zm - ui : zm, gzp ? 2.0 * zp - ui : zp);
+            } else if constexpr (!VAR) {
               au = au_const<double, 3>(a.ih2, ui, xm, xp, ym, yp, zm, zp);
             } else {
               const double kxm = o == 0 ? kl1 : K[1][i][p][0];
@@ -689,6 +744,7 @@ struct Pass {
             const bool own = rin[i] && (o ? in1[p] : in0[p]);
             if (own) sumsq += r * r;
             if constexpr (MODE == kRefine) RK[i][p][o] = own ? (float)(r * a.inv_scale) : 0.0f;
+            if constexpr (MODE == kFvJacobi) JV[i][p][o] = ui + a.coef * r;
           }
         }
       }
@@ -703,7 +759,8 @@ struct Pass {
       stepfn(IC<1>{}, s);
       ++s;
     }
-    if (MODE == kRefine) store(z1 - 1);  // queue slot 0 holds plane z1-1
+    if (MODE == kRefine || MODE == kFvJacobi) store(z1 - 1);  // queue slot 0 holds plane z1-1
+    if constexpr (MODE == kFvJacobi) return;  // no norm
 
 #pragma unroll
     for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
@@ -936,6 +993,51 @@ void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double
     fill(a);
     run_pass<false, kRefine>(s, a, partial, out);
   }
+}
+
+namespace {
+// Shape of the finite-volume passes: the norm and refinement shape, 256-column tiles from
+// N = 256 on (two per row at N = 512), 128 columns below.
+template <int MODE, typename Fill>
+void launch_fv(hipStream_t s, int N, double* partial, double* out, Fill fill)
+{
+  auto go = [&](auto cpc) {
+    constexpr int CP = decltype(cpc)::value;
+    using C = Pass<false, MODE, MG_PASS_W, MG_PASS_RPW, CP>;
+    auto kern = k_pass<false, MODE, MG_PASS_W, MG_PASS_RPW, CP>;
+    typename C::Args a{};
+    fill(a);
+    a.n = N + 2;
+    a.tiles_x = (N + C::BX - 1) / C::BX;
+    a.tiles_y = (N + C::BY - 1) / C::BY;
+    const int per = a.tiles_x * a.tiles_y;
+    a.zlen = best_zlen(per, N, 2, capacity_of(kern, 64 * MG_PASS_W), kStreamPartials);
+    const int blocks = per * ((N + a.zlen - 1) / a.zlen);
+    a.partial = partial;
+    kern<<<blocks, 64 * MG_PASS_W, 0, s>>>(a);
+    if (MODE == kFvNorm) k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
+  };
+  if (N > 128) go(IC<2>{});
+  else go(IC<1>{});
+}
+}  // namespace
+
+bool fv_tiled_supported(int N) { return N >= 128; }
+
+void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double* f,
+                     const double* u, double* uout, double* partial)
+{
+  launch_fv<kFvJacobi>(s, N, partial, nullptr, [&](auto& a) {
+    a.f = f; a.u = u; a.out = uout; a.ih2 = 1.0 / (h * h); a.coef = omega * (h * h / 6.0);
+  });
+}
+
+void fv_norm2_tiled(hipStream_t s, int N, double h, const double* f, const double* u,
+                    double* partial, double* out)
+{
+  launch_fv<kFvNorm>(s, N, partial, out, [&](auto& a) {
+    a.f = f; a.u = u; a.ih2 = 1.0 / (h * h);
+  });
 }
 
 template void restrict_residual_tiled<double>(hipStream_t, int, double, const double*,

@@ -1,5 +1,5 @@
 """Host side of the C ABI (no GPU): the library loads, exports every function that
-include/mg.h declares, validates grid descriptions and sizes workspaces without any HIP
+include/*.h declares, validates grid descriptions and sizes workspaces without any HIP
 call."""
 import ctypes
 import os
@@ -8,15 +8,20 @@ import re
 import pytest
 
 from paper_2403_08063_amd import _lib
-from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgGrid
+from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgFvGrid, MgGrid
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "mg.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(mg(?:fv)?_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_and_binding_agree():
@@ -93,3 +98,35 @@ def test_setup_rejects_bad_arguments_before_gpu_work():
     assert lib.mg_setup(ctypes.byref(g), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(out)) == MG_EINVAL
     assert "aligned" in _lib.last_error(None)
     assert lib.mg_solve(None, None, None, 1e-10, None, None) == MG_EINVAL
+
+
+# ---------------------------------------------------------------- finite-volume scheme
+def fv_bytes(**kw):
+    g = dict(N=512, levels=8, nu1=3, nu2=3, coarse_iters=256, omega=0.8, max_cycles=35)
+    g.update(kw)
+    return _lib.lib().mgfv_workspace_bytes(ctypes.byref(MgFvGrid(**g)))
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(N=4, levels=1), dict(N=64, levels=5), dict(N=2048, levels=10)])
+def test_fv_valid_grids(kw):
+    assert fv_bytes(**kw) > 0
+
+
+@pytest.mark.parametrize("kw", [dict(N=96), dict(N=2), dict(N=4096, levels=11), dict(levels=0),
+                                dict(levels=10), dict(nu1=-1), dict(coarse_iters=-1),
+                                dict(omega=0.0), dict(omega=2.0), dict(max_cycles=0)])
+def test_fv_invalid_grids_need_no_workspace(kw):
+    assert fv_bytes(**kw) == 0
+
+
+def test_fv_workspace_size():
+    """Second buffer on every level plus correction and right-hand side below the finest,
+    each (N_l + 2)^3 doubles (256-byte aligned), plus partial sums and scalars."""
+    N, levels = 64, 5
+    want = 0
+    for l in range(levels):
+        m = (N >> l) + 2
+        per = -(-(m ** 3 * 8) // 256) * 256
+        want += per * (1 if l == 0 else 3)
+    got = fv_bytes(N=N, levels=levels)
+    assert want <= got <= want + 16384 * 8 + 2048
