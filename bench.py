@@ -14,9 +14,15 @@ Also reported:
   - HBM traffic per launch from rocprofv3 counters committed under profiles/ (null if
     absent or taken on different kernel source);
   - the CPU oracle on a bounded sample of the same workload (one FP64 V-cycle and one
-    residual norm, scaled by the FP64 cycle count).
+    residual norm, scaled by the FP64 cycle count);
+  - the paper's own benchmark solver (Sect. 5-6) on a uniform cell-centred grid of 512^3
+    cells ("fv_benchmark"): the fine-level damped-Jacobi sweep in GLUP/s against the
+    paper's light-speed model (24 B per cell update: load u, load f, store u), the average
+    time of a V(3,3) cycle over 100 cycles with 256 coarsest iterations (Sect. 6), and the
+    L2 error of the harmonic problem (Eq. 1-2) at 256^3 and 512^3 cells with its
+    grid-convergence ratio kappa (Eq. 3).  --no-fv skips it.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--n 513]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fv] [--n 513]
 
 HBM traffic of the fine-level smoother (two counter runs, then a summary):
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py --pmc-sample
@@ -184,6 +190,74 @@ def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24):
     print("\n".join(head + [""] + lines))
 
 
+def fv_benchmark(dev, copy_gbs: float, N: int = 512, cycles: int = 100):
+    """The paper's benchmark solver on N^3 cells (see the module docstring)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_08063_amd import FVMultigrid, inputs
+
+    levels = max(1, N.bit_length() - 2)  # coarsest 4^3 cells
+    mg = FVMultigrid(N, levels, device=dev)
+    stream = mg.stream
+    f = torch.from_numpy(inputs.fv_uniform(N, 11)).to(dev)
+    u = torch.zeros_like(f)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # fine-level Jacobi sweeps alone (20 sweeps, out of place between u and the workspace)
+    sweeps = 20
+    mg.jacobi(0, f, u, sweeps)
+    ms = []
+    for _ in range(3):
+        ev0.record(stream)
+        mg.jacobi(0, f, u, sweeps)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    t_sweep = float(np.median(ms)) / sweeps
+    cells = N ** 3
+    glups = cells / (t_sweep * 1e-3) / 1e9
+    gbs = 24 * cells / (t_sweep * 1e-3) / 1e9
+    # V(3,3) cycles with 256 coarsest iterations (Sect. 6)
+    mg.vcycle(f, u)
+    ev0.record(stream)
+    for _ in range(cycles):
+        mg.vcycle(f, u)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_cycle = ev0.elapsed_time(ev1) / cycles
+    del f, u
+    # the harmonic problem (Eq. 1-2): 35 cycles, error against the exact solution
+    errs = {}
+    for n_cells in (N // 2, N):
+        u0, exact = inputs.fv_harmonic(n_cells)
+        m2 = FVMultigrid(n_cells, max(1, n_cells.bit_length() - 2), device=dev)
+        fz = torch.zeros(u0.shape, dtype=torch.float64, device=dev)
+        ug, info = m2.solve(fz, torch.from_numpy(u0).to(dev), tol=1e-16)
+        e = ug[1:-1, 1:-1, 1:-1] - torch.from_numpy(exact[1:-1, 1:-1, 1:-1]).to(dev)
+        errs[n_cells] = (float(torch.sqrt(torch.sum(e * e) / n_cells ** 3)), info.cycles,
+                         info.relres)
+        m2.close()
+        del fz, ug, e
+    mg.close()
+    return {
+        "workload": f"cell-centred FV Poisson on {N}^3 cells of [0,1]^3, V(3,3) damped Jacobi "
+                    f"(omega 0.8), {levels} levels down to 4^3 cells, 256 coarsest iterations",
+        "jacobi_ms_per_sweep": round(t_sweep, 4),
+        "jacobi_glups": round(glups, 1),
+        "jacobi_algorithmic_gbs": round(gbs, 1),
+        "jacobi_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "jacobi_frac_of_copy": round(gbs / copy_gbs, 4),
+        "light_speed_glups_peak_24B": round(light_speed_glups(HBM_PEAK_GBS, 24), 1),
+        "light_speed_glups_copy_24B": round(light_speed_glups(copy_gbs, 24), 1),
+        "vcycle_ms": round(t_cycle, 3),
+        "vcycles_timed": cycles,
+        "harmonic_l2_error": {str(k): v[0] for k, v in errs.items()},
+        "harmonic_cycles": {str(k): v[1] for k, v in errs.items()},
+        "harmonic_residual_norm": {str(k): v[2] for k, v in errs.items()},
+        "harmonic_kappa": round(errs[N][0] / errs[N // 2][0], 4),
+    }
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -240,6 +314,9 @@ def main():
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fv", action="store_true")
+    ap.add_argument("--fv-only", action="store_true",
+                    help="run only the paper-benchmark (cell-centred FV) leg, print its record")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", nargs="+", metavar=("TRACE_DIR", "BENCH_LOG"))
@@ -252,6 +329,24 @@ def main():
         return
     if args.pmc_sample:
         pmc_sample(args.n)
+        return
+    if args.fv_only:
+        import torch
+
+        dev = torch.device("cuda:0")
+        a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        mc = []
+        for _ in range(4):
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            mc.append(e0.elapsed_time(e1))
+        del a, b
+        copy_gbs = 2 * CALIB_BYTES / (min(mc[1:]) * 1e-3) / 1e9
+        print(json.dumps({"copy_gbs": round(copy_gbs, 1), **fv_benchmark(dev, copy_gbs)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
@@ -413,6 +508,14 @@ def main():
             "launch_ms": round(t_launch32, 4),
         },
     }
+    if not args.no_fv:
+        print("bench: paper benchmark solver (cell-centred FV, 512^3 cells)", file=sys.stderr,
+              flush=True)
+        del mg32, u32, us, f32, u32s
+        torch.cuda.empty_cache()
+        rec["fv_benchmark"] = fv_benchmark(dev, copy_gbs)
+        print(f"bench: fv jacobi {rec['fv_benchmark']['jacobi_glups']} GLUP/s, V(3,3) "
+              f"{rec['fv_benchmark']['vcycle_ms']} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(f_np, levels, info64.cycles)
