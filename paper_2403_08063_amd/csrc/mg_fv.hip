@@ -151,48 +151,45 @@ __device__ __forceinline__ double fv_apply_at(int N, double ih2, const double* _
   return s * ih2;
 }
 
-__device__ __forceinline__ void cell_of(size_t t, int N, int& z, int& y, int& x)
-{
-  x = 1 + (int)(t % (size_t)N);
-  y = 1 + (int)((t / (size_t)N) % (size_t)N);
-  z = 1 + (int)(t / ((size_t)N * N));
-}
+// One-thread-per-entry kernels run on a 3D grid: x from blockIdx.x and the thread, y and z
+// from blockIdx.y and blockIdx.z (no index division).
+constexpr int kFvRowThreads = 128;
 
-__global__ void __launch_bounds__(256)
+dim3 grid3(int xs, int ys, int zs) { return dim3((unsigned)((xs + kFvRowThreads - 1) / kFvRowThreads), ys, zs); }
+
+__global__ void __launch_bounds__(kFvRowThreads)
     k_fv_jacobi(int N, double ih2, double coef, const double* __restrict__ f,
                 const double* __restrict__ u, double* __restrict__ uout)
 {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)N * N * N) return;
-  int z, y, x;
-  cell_of(t, N, z, y, x);
+  const int x = 1 + blockIdx.x * kFvRowThreads + threadIdx.x, y = 1 + blockIdx.y, z = 1 + blockIdx.z;
+  if (x > N) return;
   const size_t i = fidx(N + 2, z, y, x);
   const double r = f[i] - fv_apply_at(N, ih2, u, z, y, x);
   uout[i] = u[i] + coef * r;
 }
 
 // r on all (N+2)^3 entries: f - A u on the cells, 0 on the ghost layer
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFvRowThreads)
     k_fv_residual(int N, double ih2, const double* __restrict__ f, const double* __restrict__ u,
                   double* __restrict__ r)
 {
   const int m = N + 2;
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)m * m * m) return;
-  const int x = (int)(t % (size_t)m), y = (int)((t / (size_t)m) % (size_t)m), z = (int)(t / ((size_t)m * m));
+  const int x = blockIdx.x * kFvRowThreads + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= m) return;
+  const size_t t = fidx(m, z, y, x);
   const bool cell = x >= 1 && x <= N && y >= 1 && y <= N && z >= 1 && z <= N;
   r[t] = cell ? f[t] - fv_apply_at(N, ih2, u, z, y, x) : 0.0;
 }
 
 // fc on all (Nc+2)^3 entries: the mean of the 8 children's residuals, 0 on the ghost layer
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFvRowThreads)
     k_fv_restrict(int Nc, double ih2, const double* __restrict__ f, const double* __restrict__ u,
                   double* __restrict__ fc)
 {
   const int mc = Nc + 2, N = 2 * Nc, m = N + 2;
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)mc * mc * mc) return;
-  const int X = (int)(t % (size_t)mc), Y = (int)((t / (size_t)mc) % (size_t)mc), Z = (int)(t / ((size_t)mc * mc));
+  const int X = blockIdx.x * kFvRowThreads + threadIdx.x, Y = blockIdx.y, Z = blockIdx.z;
+  if (X >= mc) return;
+  const size_t t = fidx(mc, Z, Y, X);
   if (X < 1 || X > Nc || Y < 1 || Y > Nc || Z < 1 || Z > Nc) {
     fc[t] = 0.0;
     return;
@@ -222,25 +219,32 @@ __device__ __forceinline__ double fv_coarse_value(int Nc, const double* __restri
 }
 
 // u += P e on the fine cells: per axis 3/4 from the parent, 1/4 from its neighbour on the
-// fine cell's side
-__global__ void __launch_bounds__(256)
+// fine cell's side.  One thread per fine column pair (2X-1, 2X), the two children of coarse
+// column X: they share the parent's y and z weights and need the coarse columns X-1, X, X+1;
+// each cell sums its 8 terms in the order z, y, x (parent first).
+__global__ void __launch_bounds__(kFvRowThreads)
     k_fv_prolong(int Nc, const double* __restrict__ e, double* __restrict__ u)
 {
   const int N = 2 * Nc;
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)N * N * N) return;
-  int z, y, x;
-  cell_of(t, N, z, y, x);
-  const int P0 = (z + 1) / 2, P1 = (y + 1) / 2, P2 = (x + 1) / 2;
-  const int Q0 = (z & 1) ? P0 - 1 : P0 + 1, Q1 = (y & 1) ? P1 - 1 : P1 + 1, Q2 = (x & 1) ? P2 - 1 : P2 + 1;
-  double s = 0.0;
+  const int X = 1 + blockIdx.x * kFvRowThreads + threadIdx.x, y = 1 + blockIdx.y, z = 1 + blockIdx.z;
+  if (X > Nc) return;
+  const int P0 = (z + 1) / 2, P1 = (y + 1) / 2;
+  const int Q0 = (z & 1) ? P0 - 1 : P0 + 1, Q1 = (y & 1) ? P1 - 1 : P1 + 1;
+  double v[2][2][3];  // [z: parent, side][y: parent, side][x: X-1, X, X+1]
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int d = 0; d < 3; ++d) v[a][b][d] = fv_coarse_value(Nc, e, a ? Q0 : P0, b ? Q1 : P1, X - 1 + d);
+  double s0 = 0.0, s1 = 0.0;  // cells 2X-1 (side X-1) and 2X (side X+1)
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int c = 0; c < 2; ++c) {
         const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (c ? 0.25 : 0.75);
-        s += w * fv_coarse_value(Nc, e, a ? Q0 : P0, b ? Q1 : P1, c ? Q2 : P2);
+        s0 += w * v[a][b][c ? 0 : 1];
+        s1 += w * v[a][b][c ? 2 : 1];
       }
-  u[fidx(N + 2, z, y, x)] += s;
+  const size_t i = fidx(N + 2, z, y, 2 * X - 1);
+  u[i] += s0;
+  u[i + 1] += s1;
 }
 
 // per-block sums of (f - A u)^2 over the cells (fixed grid: the summation order does not
@@ -251,11 +255,12 @@ __global__ void __launch_bounds__(256)
 {
   __shared__ double part[4];
   const size_t total = (size_t)N * N * N;
+  const int lg = __builtin_ctz((unsigned)N);  // N is a power of two
   double acc = 0.0;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (size_t)gridDim.x * blockDim.x) {
-    int z, y, x;
-    cell_of(t, N, z, y, x);
+    const int x = 1 + (int)(t & (size_t)(N - 1)), y = 1 + (int)((t >> lg) & (size_t)(N - 1));
+    const int z = 1 + (int)(t >> (2 * lg));
     const double r = f[fidx(N + 2, z, y, x)] - fv_apply_at(N, ih2, u, z, y, x);
     acc += r * r;
   }
@@ -313,8 +318,6 @@ __global__ void __launch_bounds__(kFvCoarseThreads)
   }
 }
 
-unsigned blocks_for(size_t count) { return (unsigned)((count + 255) / 256); }
-
 // ---------------------------------------------------------------- level operations
 double jacobi_coef(const mgfv_ctx* c, const FvLevel& L) { return c->g.omega * (L.h * L.h / 6.0); }
 
@@ -329,8 +332,8 @@ double* smooth(mgfv_ctx* c, int l, double* u, double* t, const double* f, int sw
     if (mgk::fv_tiled_supported(L.N))
       mgk::fv_jacobi_tiled(c->s, L.N, L.h, c->g.omega, f, cur, oth, c->partial);
     else
-      k_fv_jacobi<<<blocks_for((size_t)L.N * L.N * L.N), 256, 0, c->s>>>(L.N, ih2, jacobi_coef(c, L),
-                                                                         f, cur, oth);
+      k_fv_jacobi<<<grid3(L.N, L.N, L.N), kFvRowThreads, 0, c->s>>>(L.N, ih2, jacobi_coef(c, L),
+                                                                   f, cur, oth);
     double* x = cur;
     cur = oth;
     oth = x;
@@ -350,18 +353,24 @@ void coarse_solve(mgfv_ctx* c, int l, const double* f, double* u)
   if (r != u) mgk::copy<double>(c->s, L.cnt, r, u);
 }
 
+// fc = restriction of f - A u; the streaming pass (N >= 128) leaves fc's ghost layer as it
+// is (zero in the workspace), the per-cell kernel writes it as 0
 void restrict_residual(mgfv_ctx* c, int l, const double* f, const double* u, double* fc)
 {
   const FvLevel& L = c->lv[l];
   const int Nc = L.N / 2;
-  const size_t cntc = (size_t)(Nc + 2) * (Nc + 2) * (Nc + 2);
-  k_fv_restrict<<<blocks_for(cntc), 256, 0, c->s>>>(Nc, 1.0 / (L.h * L.h), f, u, fc);
+  if (mgk::fv_tiled_supported(L.N)) {
+    mgk::fv_restrict_tiled(c->s, L.N, L.h, f, u, fc, c->partial);
+    return;
+  }
+  k_fv_restrict<<<grid3(Nc + 2, Nc + 2, Nc + 2), kFvRowThreads, 0, c->s>>>(Nc, 1.0 / (L.h * L.h),
+                                                                          f, u, fc);
 }
 
 void prolong(mgfv_ctx* c, int l, const double* ec, double* u)
 {
   const FvLevel& L = c->lv[l];
-  k_fv_prolong<<<blocks_for((size_t)L.N * L.N * L.N), 256, 0, c->s>>>(L.N / 2, ec, u);
+  k_fv_prolong<<<grid3(L.N / 2, L.N, L.N), kFvRowThreads, 0, c->s>>>(L.N / 2, ec, u);
 }
 
 void norm2(mgfv_ctx* c, const double* f, const double* u)
@@ -478,7 +487,8 @@ mg_status mgfv_residual(mgfv_ctx* c, int level, const double* f, const double* u
   if (mg_status st = level_args(c, level, false)) return st;
   if (!f || !u || !r) return fv_fail(c, MG_EINVAL, "f, u and r must be non-NULL");
   const FvLevel& L = c->lv[level];
-  k_fv_residual<<<blocks_for(L.cnt), 256, 0, c->s>>>(L.N, 1.0 / (L.h * L.h), f, u, r);
+  k_fv_residual<<<grid3(L.N + 2, L.N + 2, L.N + 2), kFvRowThreads, 0, c->s>>>(L.N, 1.0 / (L.h * L.h),
+                                                                             f, u, r);
   return fv_launch_check(c, "residual");
 }
 
@@ -487,6 +497,7 @@ mg_status mgfv_restrict_residual(mgfv_ctx* c, int level, const double* f, const 
 {
   if (mg_status st = level_args(c, level, true)) return st;
   if (!f || !u || !fc) return fv_fail(c, MG_EINVAL, "f, u and fc must be non-NULL");
+  if (mgk::fv_tiled_supported(c->lv[level].N)) mgk::zero_boundary(c->s, 3, c->lv[level + 1].N + 2, fc);
   restrict_residual(c, level, f, u, fc);
   return fv_launch_check(c, "restriction");
 }

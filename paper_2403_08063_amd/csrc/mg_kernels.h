@@ -134,6 +134,10 @@ bool fv_tiled_supported(int N);
 // one damped Jacobi sweep, uout = u + omega h^2/6 (f - A u) on the cells (ghosts untouched)
 void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double* f,
                      const double* u, double* uout, double* partial);
+// fc = mean of the 8 children's residuals f - A u on the coarse cells (N/2 per side);
+// fc's ghost layer is not written
+void fv_restrict_tiled(hipStream_t s, int N, double h, const double* f, const double* u,
+                       double* fc, double* partial);
 // out = sum over cells of (f - A u)^2 (partial: kStreamPartials doubles)
 void fv_norm2_tiled(hipStream_t s, int N, double h, const double* f, const double* u,
                     double* partial, double* out);

@@ -35,7 +35,7 @@ namespace {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4 };
+enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4, kFvRestrict = 5 };
 
 // (A u)_i of the cell-centred finite-volume operator from the six neighbour values (ghost
 // neighbours already replaced by 2 g - u_i), in the order -x, +x, -y, +y, -z, +z.
@@ -423,9 +423,13 @@ struct Stream {
 // kFvJacobi): N^3 cells with a ghost layer, n = N + 2 values per side.  The ghost layer
 // holds the Dirichlet value at the face centre, and a ghost neighbour enters the operator
 // as 2 g - u_i; kFvJacobi writes the damped Jacobi update u + coef (f - A u) out of place.
+// kFvRestrict writes the mean of the 8 children's residuals to the coarse level: a lane's
+// column pair, a wave's row pair and a pair of consecutive planes (z-chunks of even length
+// starting on odd planes) are the children of one coarse cell, summed in the order z, y, x.
 template <bool VAR, int MODE, int W, int RPW, int CP>
 struct Pass {
-  static constexpr bool FV = MODE == kFvNorm || MODE == kFvJacobi;
+  static constexpr bool FV = MODE == kFvNorm || MODE == kFvJacobi || MODE == kFvRestrict;
+  static_assert(MODE != kFvRestrict || RPW % 2 == 0, "row pairs of the restriction");
   static_assert(!(FV && VAR), "the finite-volume scheme has a constant coefficient");
   static_assert(W >= 2, "the first and the last wave load the tile's halo rows");
   static constexpr int BX = 128 * CP, BY = W * RPW;
@@ -644,6 +648,16 @@ struct Pass {
 
     float RK[RPW][CP][2];
     double JV[MODE == kFvJacobi ? RPW : 1][CP][2];
+    double RA[MODE == kFvRestrict ? RPW / 2 : 1][CP];  // coarse sums of the plane pair
+    // coarse level (restriction): column byte offsets, dropped where the pair is not owned
+    uint32_t cco[CP];
+    const int mc = (n - 2) / 2 + 2;
+    const uint32_t cplane = (uint32_t)((size_t)mc * (size_t)mc * 8u);
+#pragma unroll
+    for (int p = 0; p < CP; ++p) {
+      const int c = ox + 128 * p + 2 * lane;
+      cco[p] = in0[p] ? (uint32_t)((c + 1) / 2) * 8u : 0x80000000u;
+    }
     double sumsq = 0.0;
     auto store = [&](int sp) {  // u_out from queue slot 0, r32 from RK
       const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
@@ -745,6 +759,24 @@ struct Pass {
             if (own) sumsq += r * r;
             if constexpr (MODE == kRefine) RK[i][p][o] = own ? (float)(r * a.inv_scale) : 0.0f;
             if constexpr (MODE == kFvJacobi) JV[i][p][o] = ui + a.coef * r;
+            if constexpr (MODE == kFvRestrict) {
+              // steps of parity 0 are the odd (first) planes of a coarse cell's children
+              if (bb == 0 && i % 2 == 0 && o == 0) RA[i / 2][p] = 0.0;
+              RA[i / 2][p] = RA[i / 2][p] + r;
+            }
+          }
+        }
+      }
+      if constexpr (MODE == kFvRestrict) {
+        if (bb == 1) {  // second plane of the pair: the coarse values are complete
+          const PlaneBuf bc = plane_buf(a.out, (size_t)(s / 2) * cplane, cplane);
+#pragma unroll
+          for (int i = 0; i < RPW; i += 2) {
+            if (!rin[i]) continue;
+            const int Y = (oy + w * RPW + i + 1) / 2;
+            const uint32_t row = (uint32_t)(Y * mc) * 8u;
+#pragma unroll
+            for (int p = 0; p < CP; ++p) buf_store(RA[i / 2][p] / 8.0, bc, cco[p], row);
           }
         }
       }
@@ -760,7 +792,7 @@ struct Pass {
       ++s;
     }
     if (MODE == kRefine || MODE == kFvJacobi) store(z1 - 1);  // queue slot 0 holds plane z1-1
-    if constexpr (MODE == kFvJacobi) return;  // no norm
+    if constexpr (MODE == kFvJacobi || MODE == kFvRestrict) return;  // no norm
 
 #pragma unroll
     for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
@@ -1012,6 +1044,7 @@ void launch_fv(hipStream_t s, int N, double* partial, double* out, Fill fill)
     a.tiles_y = (N + C::BY - 1) / C::BY;
     const int per = a.tiles_x * a.tiles_y;
     a.zlen = best_zlen(per, N, 2, capacity_of(kern, 64 * MG_PASS_W), kStreamPartials);
+    if (MODE == kFvRestrict) a.zlen += a.zlen & 1;  // chunks start on odd planes
     const int blocks = per * ((N + a.zlen - 1) / a.zlen);
     a.partial = partial;
     kern<<<blocks, 64 * MG_PASS_W, 0, s>>>(a);
@@ -1029,6 +1062,14 @@ void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double*
 {
   launch_fv<kFvJacobi>(s, N, partial, nullptr, [&](auto& a) {
     a.f = f; a.u = u; a.out = uout; a.ih2 = 1.0 / (h * h); a.coef = omega * (h * h / 6.0);
+  });
+}
+
+void fv_restrict_tiled(hipStream_t s, int N, double h, const double* f, const double* u,
+                       double* fc, double* partial)
+{
+  launch_fv<kFvRestrict>(s, N, partial, nullptr, [&](auto& a) {
+    a.f = f; a.u = u; a.out = fc; a.ih2 = 1.0 / (h * h);
   });
 }
 
