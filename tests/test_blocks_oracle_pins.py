@@ -1,0 +1,176 @@
+"""Pins of the refined-block oracle (oracle/blocks.py): the paper's 2:1 refined layout and its
+ghost-layer fills (Sect. 3, Sect. 5), checked against what the mathematics and the paper fix.
+
+  - the layout has the paper's block counts (56 on level 2, 64 on level 3) and tiles [0,1]^3;
+  - quadratic C2F (second-degree Lagrange per axis, with the -2 o remapping at block edges)
+    reproduces every triquadratic function exactly, in all nine edge/corner cases; the
+    linear and constant variants reproduce trilinear functions and constants;
+  - linear F2C (mean of the 8 fine cells, weight 0.125) reproduces trilinear functions;
+  - every fill is a partition of unity;
+  - the grid-convergence ratio kappa (Eq. 3) of the harmonic problem follows Table 1's
+    pattern: about 1, 0.5 and 0.25 for constant, linear and quadratic C2F (the quadratic within
+    the deviation of Table 1's second-order column from 0.25).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import blocks as bl
+
+B = 8
+
+
+def stored_field(B, fn):
+    """fn at the centre of every stored cell (inner and ghost) of every block."""
+    blocks = bl.layout()
+    m = B + 2
+    arr = np.zeros(len(blocks) * m ** 3)
+    A = arr.reshape(len(blocks), m, m, m)
+    i = np.arange(m) - 0.5
+    for b, (lv, idx, w) in enumerate(blocks):
+        h = w / B
+        x = idx[0] * w + i[None, None, :] * h
+        y = idx[1] * w + i[None, :, None] * h
+        z = idx[2] * w + i[:, None, None] * h
+        A[b] = fn(*np.broadcast_arrays(x, y, z))
+    return arr
+
+
+def test_layout_matches_paper_counts_and_tiles_domain():
+    blocks = bl.layout()
+    assert sum(1 for b in blocks if b[0] == 2) == 56
+    assert sum(1 for b in blocks if b[0] == 3) == 64
+    assert abs(sum(w ** 3 for (_, _, w) in blocks) - 1.0) < 1e-15
+    # no overlap: every point of a fine sampling lies in exactly one block
+    pts = (np.arange(16) + 0.5) / 16
+    for x in pts[::3]:
+        for y in pts[::5]:
+            for z in pts:
+                inside = [b for b in blocks
+                          if all(b[1][a] * b[2] <= c < (b[1][a] + 1) * b[2] for a, c in enumerate((x, y, z)))]
+                assert len(inside) == 1
+
+
+def _rows_of(kind, rows, kinds):
+    return np.unique(rows[kinds == kind])
+
+
+@pytest.mark.parametrize("order,fn", [
+    (2, lambda x, y, z: 1 + x - 2 * y + 3 * z + x * x - 2 * y * z + 0.5 * z * z + x * y + x * y * z
+     + x * x * y * z * z - 0.3 * x * x * y * y * z * z),
+    (1, lambda x, y, z: 1 + x - 2 * y + 3 * z + x * y - 2 * y * z + 0.7 * x * y * z),
+    (0, lambda x, y, z: 2.5 + 0 * x),
+])
+def test_c2f_reproduces_its_polynomial_degree(order, fn):
+    exact = stored_field(B, fn)
+    rows, cols, vals, kinds, _ = bl.ghost_map(B, order)
+    arr = exact.copy()
+    c2f = _rows_of(bl.KIND_C2F, rows, kinds)
+    arr[np.unique(rows)] = 0.0
+    bl.fill(arr, B, order)
+    # the refined cube's surface: 6 faces of 4 x 4 fine blocks, B^2 ghost cells each
+    assert c2f.size == 96 * B * B
+    assert np.abs(arr[c2f] - exact[c2f]).max() <= 1e-12 * np.abs(exact).max()
+
+
+def test_quadratic_c2f_fails_on_a_cubic():
+    """The exactness above is not vacuous: a cubic along the normal is not reproduced."""
+    fn = lambda x, y, z: (x - 0.3) ** 3 + (y - 0.6) ** 3 + (z - 0.4) ** 3  # noqa: E731
+    exact = stored_field(B, fn)
+    rows, _, _, kinds, _ = bl.ghost_map(B, 2)
+    arr = exact.copy()
+    arr[np.unique(rows)] = 0.0
+    bl.fill(arr, B, 2)
+    c2f = _rows_of(bl.KIND_C2F, rows, kinds)
+    assert np.abs(arr[c2f] - exact[c2f]).max() > 1e-7
+
+
+def test_quadratic_c2f_nine_cases_all_occur():
+    """Per C2F ghost cell, the tangential bases of the two orthogonal axes are centred,
+    remapped downwind or remapped upwind: the nine combinations (interior, 4 edges, 4 corners
+    of a segment) all occur in the layout, and each row has 27 bases."""
+    blocks = bl.layout()
+    faces = bl.face_neighbours(blocks)
+    cases = set()
+    for b, f in enumerate(faces):
+        for (ax, side), nb in f.items():
+            if nb[0] != "c2f":
+                continue
+            s1, s2 = nb[2]
+            for t1 in range(1, B + 1):
+                for t2 in range(1, B + 1):
+                    T1 = s1 * (B // 2) + (t1 - 1) // 2
+                    T2 = s2 * (B // 2) + (t2 - 1) // 2
+                    n1, _ = bl.c2f_tangential(2, T1, B, -0.25)
+                    n2, _ = bl.c2f_tangential(2, T2, B, -0.25)
+                    cases.add((n1[0], n2[0]))
+    assert cases == {(a, c) for a in (-2, -1, 0) for c in (-2, -1, 0)}
+    rows, _, _, kinds, _ = bl.ghost_map(B, 2)
+    per_row = np.bincount(rows[kinds == bl.KIND_C2F])
+    assert set(per_row[per_row > 0]) == {27}
+
+
+def test_f2c_reproduces_trilinear_and_same_level_copies():
+    fn = lambda x, y, z: 1 + x - 2 * y + 3 * z + x * y - 2 * y * z + 0.7 * x * y * z  # noqa: E731
+    exact = stored_field(B, fn)
+    rows, _, _, kinds, _ = bl.ghost_map(B, 2)
+    arr = exact.copy()
+    arr[np.unique(rows)] = 0.0
+    bl.fill(arr, B, 2)
+    assert _rows_of(bl.KIND_F2C, rows, kinds).size == 24 * B * B  # 6 faces x 4 coarse blocks
+    for kind in (bl.KIND_F2C, bl.KIND_SAME):
+        r = _rows_of(kind, rows, kinds)
+        assert r.size > 0
+        assert np.abs(arr[r] - exact[r]).max() <= 1e-13 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_fills_are_partitions_of_unity(order):
+    rows, _, vals, _, _ = bl.ghost_map(B, order)
+    sums = np.bincount(rows, weights=vals)
+    assert np.abs(sums[np.unique(rows)] - 1.0).max() <= 1e-14
+
+
+def test_jacobi_sweep_fixed_point_is_the_composite_solution():
+    """The per-block sweep with ghost fills (what the GPU path runs) leaves the solution of the
+    assembled composite system unchanged."""
+    Bs = 4
+    A, rhs = bl.composite_system(Bs, 2, bl.harmonic)
+    u = bl.solve_system(A, rhs)
+    blocks = bl.layout()
+    m = Bs + 2
+    arr = np.zeros(len(blocks) * m ** 3)
+    V = arr.reshape(len(blocks), m, m, m)
+    V[:, 1:-1, 1:-1, 1:-1] = u.reshape(len(blocks), Bs, Bs, Bs)
+    out = bl.jacobi_sweep(arr, np.zeros_like(arr), Bs, 2, g=bl.harmonic)
+    O = out.reshape(len(blocks), m, m, m)
+    assert np.abs(O[:, 1:-1, 1:-1, 1:-1] - V[:, 1:-1, 1:-1, 1:-1]).max() <= 1e-11 * np.abs(u).max()
+
+
+def read_golden(name):
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            parts = line.split()
+            rows[parts[0]] = [float(p) for p in parts[1:]]
+    return rows
+
+
+def test_kappa_pattern_of_table1():
+    """Eq. 3 on the refined layout (Sect. 5): constant C2F does not converge (kappa ~ 1),
+    linear C2F is first order (kappa between second order's 0.25 and 0.5 at these block
+    sizes, rising towards 0.5: 0.39 for 4 -> 8 cells, 0.44 for 8 -> 16), quadratic C2F is
+    second order (kappa within Table 1's deviation from 0.25)."""
+    g = read_golden("paper_table1_kappa.txt")
+    target = g["target"][0]
+    paper_dev = max(abs(v[1] - target) for key, v in g.items() if key != "target" and not np.isnan(v[1]))
+    kappa = {}
+    for order in (0, 1, 2):
+        e4 = bl.solve_harmonic(4, order)[1]
+        e8 = bl.solve_harmonic(8, order)[1]
+        kappa[order] = e8 / e4
+    assert abs(kappa[0] - 1.0) <= 0.05, kappa
+    assert 0.3 <= kappa[1] <= 0.55, kappa
+    assert abs(kappa[2] - target) <= paper_dev, kappa
