@@ -1,0 +1,90 @@
+/*
+ * mg_blocks.h -- C ABI of the 2:1 refined block layout in libmg.so: the ghost-layer exchange
+ * between blocks of different refinement levels (Angersbach, Kuckuk, Koestler, arXiv
+ * 2403.08063, Sect. 3: same-level copies, fine-to-coarse (F2C) linear interpolation,
+ * coarse-to-fine (C2F) extrapolation of constant, linear or quadratic order) on the layout
+ * of Sect. 5, with a damped-Jacobi solver of the composite cell-centred system (Eq. 1-2).
+ *
+ * Layout: [0,1]^3 split into 4^3 level-2 blocks of width 1/4, the central 2^3 of them
+ * refined into 8 level-3 blocks of width 1/8 each: 56 + 64 = 120 blocks (the counts of
+ * Sect. 5).  Every block holds B^3 cells (B even, 4 <= B <= 256; its own h = width / B),
+ * stored as (B+2)^3 doubles with a one-cell ghost layer, C order [z][y][x]; the blocks are
+ * concatenated: first the level-2 blocks in (z, y, x) order of their block index, then the
+ * level-3 blocks in (z, y, x) order of their level-3 block index.
+ *
+ * Ghost layer of a face:
+ *  - on the domain boundary: the Dirichlet value at the face centre, written by the caller
+ *    and never by the library; the operator uses 2 g - u_i there;
+ *  - towards a block of the same level: a copy of the neighbour's adjacent inner cell;
+ *  - of a level-2 block towards refined blocks (F2C): the mean of the 8 level-3 inner cells
+ *    the coarse ghost cell covers (weights 0.125);
+ *  - of a level-3 block towards a level-2 block (C2F): from the coarse block's inner cells
+ *    only, by Lagrange bases along each axis (order+1 of them): along the normal the coarse
+ *    cell at the interface and the next ones away from it, extrapolated to the fine ghost
+ *    centre a quarter coarse cell towards the face; along each tangential axis the cell and
+ *    its neighbours, evaluated at -1/4 or +1/4 coarse cell, with a base that would fall into
+ *    the coarse block's ghost region replaced by the inner cell at -2 o (Sect. 3's
+ *    remapping; order 1 takes the neighbour on the fine cell's side, or the other one at the
+ *    block edge; order 0 copies the coarse cell).
+ * The operator of every block is the 7-point finite-volume one of mg_fv.h with that block's
+ * h; damped Jacobi: u <- u + omega (h^2/6) (f - A u).
+ *
+ * Conventions as in mg.h: device pointers owned by the caller; a caller-provided workspace
+ * (mgblk_workspace_bytes, 256-byte aligned), no allocation by the library; all work on the
+ * stream given to mgblk_setup; mgblk_residual_norm2 and mgblk_solve synchronise to read norms.
+ */
+#ifndef MG_BLOCKS_H
+#define MG_BLOCKS_H
+
+#include <stddef.h>
+
+#include "mg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgblk_ctx mgblk_ctx;
+
+typedef struct {
+  int B;         /* cells per block and axis: even, 4 <= B <= 256 */
+  int order;     /* C2F extrapolation order: 0, 1 or 2 (the paper's quadratic scheme) */
+  double omega;  /* Jacobi damping, 0 < omega < 2 */
+} mgblk_grid;
+
+/* Number of blocks of the layout (120). */
+int mgblk_block_count(void);
+
+/* Bytes of device workspace (host-only); 0 if the description is invalid. */
+size_t mgblk_workspace_bytes(const mgblk_grid* grid);
+
+/* Validates, lays out the workspace and uploads the layout's face table on `stream`. */
+mg_status mgblk_setup(const mgblk_grid* grid, void* workspace, size_t bytes, void* stream,
+                      mgblk_ctx** out);
+
+void mgblk_destroy(mgblk_ctx* ctx);
+
+const char* mgblk_last_error(const mgblk_ctx* ctx);
+
+/* Fills every ghost cell not on the domain boundary of the concatenated block arrays u from
+ * the neighbouring blocks' inner cells (Sect. 3's exchange). */
+mg_status mgblk_fill(mgblk_ctx* ctx, double* u);
+
+/* `sweeps` damped Jacobi sweeps of the composite system, each preceded by a ghost fill; u in
+ * place (its domain-boundary ghosts are the Dirichlet data). */
+mg_status mgblk_jacobi(mgblk_ctx* ctx, const double* f, double* u, int sweeps);
+
+/* Fills u's ghosts, then *out = sum over all inner cells of (f - A u)^2. */
+mg_status mgblk_residual_norm2(mgblk_ctx* ctx, const double* f, double* u, double* out);
+
+/* Jacobi sweeps until the L2 residual norm is <= tol (checked every check_every sweeps) or
+ * max_sweeps ran; *sweeps and *resnorm (optional) receive the count and the last norm.
+ * MG_ENOCONV if the tolerance was not reached. */
+mg_status mgblk_solve(mgblk_ctx* ctx, const double* f, double* u, double tol, int max_sweeps,
+                      int check_every, int* sweeps, double* resnorm);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_BLOCKS_H */

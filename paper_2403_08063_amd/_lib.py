@@ -30,6 +30,9 @@ EXPORTS = [
     "mgfv_workspace_bytes", "mgfv_setup", "mgfv_destroy", "mgfv_last_error", "mgfv_jacobi",
     "mgfv_residual", "mgfv_restrict_residual", "mgfv_prolong_correct", "mgfv_coarse_solve",
     "mgfv_residual_norm2", "mgfv_vcycle", "mgfv_solve",
+    # include/mg_blocks.h
+    "mgblk_block_count", "mgblk_workspace_bytes", "mgblk_setup", "mgblk_destroy",
+    "mgblk_last_error", "mgblk_fill", "mgblk_jacobi", "mgblk_residual_norm2", "mgblk_solve",
 ]
 
 
@@ -43,6 +46,10 @@ class MgFvGrid(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("omega", ctypes.c_double),
                 ("max_cycles", ctypes.c_int)]
+
+
+class MgBlkGrid(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int), ("order", ctypes.c_int), ("omega", ctypes.c_double)]
 
 
 class MgError(RuntimeError):
@@ -66,6 +73,7 @@ def lib() -> ctypes.CDLL:
     i, d, P, S = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     G = ctypes.POINTER(MgGrid)
     FG = ctypes.POINTER(MgFvGrid)
+    BG = ctypes.POINTER(MgBlkGrid)
     PI, PD = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     sig = {
         "mg_validate": (i, [G]),
@@ -100,6 +108,15 @@ def lib() -> ctypes.CDLL:
         "mgfv_residual_norm2": (i, [P, P, P, PD]),
         "mgfv_vcycle": (i, [P, P, P]),
         "mgfv_solve": (i, [P, P, P, d, PI, PD]),
+        "mgblk_block_count": (i, []),
+        "mgblk_workspace_bytes": (S, [BG]),
+        "mgblk_setup": (i, [BG, P, S, P, ctypes.POINTER(P)]),
+        "mgblk_destroy": (None, [P]),
+        "mgblk_last_error": (ctypes.c_char_p, [P]),
+        "mgblk_fill": (i, [P, P]),
+        "mgblk_jacobi": (i, [P, P, P, i]),
+        "mgblk_residual_norm2": (i, [P, P, P, PD]),
+        "mgblk_solve": (i, [P, P, P, d, i, i, PI, PD]),
     }
     for name in EXPORTS:
         res, args = sig[name]
@@ -125,5 +142,13 @@ def check_fv(status: int, ctx=None, allow=()) -> int:
     """check() for the finite-volume contexts (their own error text)."""
     if status != MG_OK and status not in allow:
         msg = lib().mgfv_last_error(ctx)
+        raise MgError(status, msg.decode() if msg else "")
+    return status
+
+
+def check_blk(status: int, ctx=None, allow=()) -> int:
+    """check() for the refined-block contexts (their own error text)."""
+    if status != MG_OK and status not in allow:
+        msg = lib().mgblk_last_error(ctx)
         raise MgError(status, msg.decode() if msg else "")
     return status

@@ -102,6 +102,67 @@ def fv_uniform(N: int, seed: int, amplitude: float = 1.0) -> np.ndarray:
     return a
 
 
+# ---------------------------------------------------------------- refined block layout
+# The 2:1 refined layout of Sect. 5: 4^3 level-2 blocks of width 1/4 with the central 2^3
+# refined into level-3 blocks of width 1/8 (56 + 64 blocks), in the order level-2 blocks in
+# (z, y, x) order of their index, then level-3 blocks likewise; B^3 cells per block stored
+# with a ghost layer as (120, B+2, B+2, B+2).
+
+def block_list():
+    """(level, (bx, by, bz), width) of every block, in storage order."""
+    inner = (1, 2)
+    out = [(2, (bx, by, bz), 0.25) for bz in range(4) for by in range(4) for bx in range(4)
+           if not (bx in inner and by in inner and bz in inner)]
+    out += [(3, (fx, fy, fz), 0.125) for fz in range(8) for fy in range(8) for fx in range(8)
+            if fx // 2 in inner and fy // 2 in inner and fz // 2 in inner]
+    return out
+
+
+def block_positions(B: int) -> np.ndarray:
+    """(120, B+2, B+2, B+2, 3) positions (x, y, z) of every stored cell: cell centres inside;
+    a ghost cell on the domain boundary at the centre of its boundary face (its Dirichlet
+    value is taken there); other ghost cells at their (unused) cell centres."""
+    blocks = block_list()
+    m = B + 2
+    out = np.empty((len(blocks), m, m, m, 3))
+    i = np.arange(m) - 0.5
+    for b, (lv, idx, w) in enumerate(blocks):
+        per = 4 if lv == 2 else 8
+        h = w / B
+        for a in range(3):
+            c = idx[a] * w + i * h
+            if idx[a] == 0:
+                c[0] = 0.0
+            if idx[a] == per - 1:
+                c[-1] = 1.0
+            shape = [1, 1, 1]
+            shape[2 - a] = m  # array axes are [z][y][x]
+            out[b, ..., a] = np.broadcast_to(c.reshape(shape), (m, m, m))
+    return out
+
+
+def block_harmonic(B: int):
+    """The harmonic problem of Eq. 1-2 on the block layout: (u0, exact): u0 holds the Dirichlet
+    data in the domain-boundary ghosts and 0 elsewhere, exact the solution at every stored
+    position."""
+    p = block_positions(B)
+    exact = np.sin(np.pi * p[..., 0]) * np.sin(np.pi * p[..., 1]) * np.sinh(np.sqrt(2.0) * np.pi * p[..., 2])
+    u0 = np.zeros_like(exact)
+    blocks = block_list()
+    for b, (lv, idx, w) in enumerate(blocks):
+        per = 4 if lv == 2 else 8
+        for a in range(3):
+            sl_lo = [b, slice(None), slice(None), slice(None)]
+            sl_hi = [b, slice(None), slice(None), slice(None)]
+            sl_lo[3 - a] = 0
+            sl_hi[3 - a] = -1
+            if idx[a] == 0:
+                u0[tuple(sl_lo)] = exact[tuple(sl_lo)]
+            if idx[a] == per - 1:
+                u0[tuple(sl_hi)] = exact[tuple(sl_hi)]
+    return u0, exact
+
+
 def gaussian_random_field(dim: int, n: int, seed: int, corr: float = 0.1,
                           sigma: float = 1.0) -> np.ndarray:
     """Stationary Gaussian field with covariance sigma^2 exp(-r^2 / (2 corr^2)).

@@ -20,7 +20,7 @@ def declared_functions():
             continue
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names |= set(re.findall(r"\b(mg(?:fv)?_[a-z0-9_]+)\s*\(", text))
+        names |= set(re.findall(r"\b(mg(?:fv|blk)?_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 
