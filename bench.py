@@ -20,7 +20,11 @@ Also reported:
     paper's light-speed model (24 B per cell update: load u, load f, store u), the average
     time of a V(3,3) cycle over 100 cycles with 256 coarsest iterations (Sect. 6), and the
     L2 error of the harmonic problem (Eq. 1-2) at 256^3 and 512^3 cells with its
-    grid-convergence ratio kappa (Eq. 3).  --no-fv skips it.
+    grid-convergence ratio kappa (Eq. 3).  --no-fv skips it;
+  - the 2:1 refined block layout of Sect. 5 ("refined_blocks", 56 + 64 blocks): time of the
+    ghost exchange (Sect. 3: same-level, F2C, quadratic C2F) and of a composite Jacobi sweep
+    at 64^3 cells per block, and kappa (Eq. 3) from GPU solves at 8^3 and 16^3 cells per block
+    with quadratic C2F (Table 1's second-order column).  --no-blocks skips it.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fv] [--n 513]
 
@@ -258,6 +262,74 @@ def fv_benchmark(dev, copy_gbs: float, N: int = 512, cycles: int = 100):
     }
 
 
+def refined_benchmark(dev, B: int = 64):
+    """The refined block layout (see the module docstring)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_08063_amd import RefinedBlocks, inputs
+
+    rb = RefinedBlocks(B, 2, device=dev)
+    stream = rb.stream
+    u0, _ = inputs.block_harmonic(B)
+    u = torch.from_numpy(u0).to(dev)
+    f = torch.zeros_like(u)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50
+    rb.fill(u)
+    ev0.record(stream)
+    for _ in range(reps):
+        rb.fill(u)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_fill = ev0.elapsed_time(ev1) / reps
+    rb.jacobi(f, u, 20)
+    ms = []
+    for _ in range(3):
+        ev0.record(stream)
+        rb.jacobi(f, u, 20)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    t_sweep = float(np.median(ms)) / 20  # fill + sweep
+    cells = 120 * B ** 3
+    rb.close()
+    del u, f
+    errs, sweeps, t_solve = {}, {}, {}
+    hb = None
+    for Bs in (8, 16):
+        u0, exact = inputs.block_harmonic(Bs)
+        r2 = RefinedBlocks(Bs, 2, device=dev)
+        fz = torch.zeros(u0.shape, dtype=torch.float64, device=dev)
+        ug = torch.from_numpy(u0).to(dev)
+        r0 = np.sqrt(r2.residual_norm2(fz, ug))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ug, info = r2.solve(fz, ug, tol=1e-11 * r0, check_every=2000)
+        torch.cuda.synchronize()
+        t_solve[Bs] = (time.perf_counter() - t0) * 1e3
+        hb = np.array([w / Bs for (_, _, w) in inputs.block_list()])
+        e = (ug.cpu().numpy() - exact)[:, 1:-1, 1:-1, 1:-1].reshape(120, -1)
+        errs[Bs] = float(np.sqrt(np.sum(hb ** 3 * np.sum(e ** 2, axis=1))))
+        sweeps[Bs] = info.cycles
+        r2.close()
+    return {
+        "workload": f"2:1 refined layout of [0,1]^3 (56 level-2 + 64 level-3 blocks), {B}^3 cells "
+                    "per block, quadratic C2F / linear F2C ghost exchange, damped Jacobi",
+        "cells": cells,
+        "ghost_fill_ms": round(t_fill, 4),
+        "ghost_cells_per_fill": 120 * 6 * B * B,
+        "jacobi_sweep_with_fill_ms": round(t_sweep, 4),
+        "jacobi_glups": round(cells / (t_sweep * 1e-3) / 1e9, 1),
+        "jacobi_algorithmic_gbs": round(24 * cells / (t_sweep * 1e-3) / 1e9, 1),
+        "harmonic_l2_error": {str(k): v for k, v in errs.items()},
+        "harmonic_jacobi_sweeps": {str(k): v for k, v in sweeps.items()},
+        "harmonic_solve_ms": {str(k): round(v, 1) for k, v in t_solve.items()},
+        "kappa_8_16": round(errs[16] / errs[8], 4),
+        "paper_table1_l2_error_block16": 3.017e-3,
+    }
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -315,6 +387,9 @@ def main():
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fv", action="store_true")
+    ap.add_argument("--no-blocks", action="store_true")
+    ap.add_argument("--blocks-only", action="store_true",
+                    help="run only the refined-block leg, print its record")
     ap.add_argument("--fv-only", action="store_true",
                     help="run only the paper-benchmark (cell-centred FV) leg, print its record")
     ap.add_argument("--pmc-sample", action="store_true")
@@ -329,6 +404,11 @@ def main():
         return
     if args.pmc_sample:
         pmc_sample(args.n)
+        return
+    if args.blocks_only:
+        import torch
+
+        print(json.dumps(refined_benchmark(torch.device("cuda:0"))), flush=True)
         return
     if args.fv_only:
         import torch
@@ -516,6 +596,11 @@ def main():
         rec["fv_benchmark"] = fv_benchmark(dev, copy_gbs)
         print(f"bench: fv jacobi {rec['fv_benchmark']['jacobi_glups']} GLUP/s, V(3,3) "
               f"{rec['fv_benchmark']['vcycle_ms']} ms", file=sys.stderr, flush=True)
+    if not args.no_blocks:
+        print("bench: refined block layout (Sect. 3/5)", file=sys.stderr, flush=True)
+        rec["refined_blocks"] = refined_benchmark(dev)
+        print(f"bench: refined blocks fill {rec['refined_blocks']['ghost_fill_ms']} ms, kappa "
+              f"{rec['refined_blocks']['kappa_8_16']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(f_np, levels, info64.cycles)
