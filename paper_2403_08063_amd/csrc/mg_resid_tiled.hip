@@ -1,15 +1,16 @@
 // Streaming residual kernels for large 3D levels on gfx950: one pass over u and f per call.
 //
-//  - restriction: fc = FW(f - A u) on the coarse interior (full weighting, the tensor
-//    product of (1/4, 1/2, 1/4));
-//  - norm: sum over interior nodes of (f - A u)^2, per-workgroup partial sums reduced
-//    afterwards in a fixed order; optionally with the interior of u read as 0 (the norm
-//    of the full right-hand side);
-//  - refinement pass: u_out = u + s e (e in float), r = f - A u_out, r32 = r * inv_scale
-//    (float), sum of r^2 -- the FP64 update, residual, norm and down-cast of one step of
-//    iterative refinement fused in one pass.
+//  - restriction (Stream): fc = FW(f - A u) on the coarse interior (full weighting, the
+//    tensor product of (1/4, 1/2, 1/4));
+//  - norm (Pass, below): sum over interior nodes of (f - A u)^2, per-workgroup partial sums
+//    reduced afterwards in a fixed order; optionally with the interior of u read as 0 (the
+//    norm of the full right-hand side);
+//  - refinement pass (Pass): u_out = u + s e (e in float), r = f - A u_out,
+//    r32 = r * inv_scale (float), sum of r^2 -- the FP64 update, residual, norm and down-cast
+//    of one step of iterative refinement fused in one pass;
+//  - the cell-centred finite-volume sweep, norm and restriction (Pass).
 //
-// Decomposition (as in the fused smoother): a workgroup owns a tile of 128 columns x
+// Restriction decomposition (as in the fused smoother): a workgroup owns a tile of 128 columns x
 // W*RPW rows of a z-chunk and streams through its planes; lane l of wave w holds columns
 // 2l, 2l+1 of rows w*RPW .. w*RPW+RPW-1.  A lane keeps u on the planes s-1, s, s+1 in
 // registers (the residual's z-neighbours), takes x-neighbours from adjacent lanes by DPP
@@ -53,33 +54,24 @@ __device__ __forceinline__ double fv_au(double ih2, double ui, double v0, double
 
 template <typename T, bool VAR, int MODE, int W, int RPW, int PD>
 struct Stream {
+  static_assert(MODE == kRestrict, "the streaming restriction (norms and refinement: Pass)");
   static_assert(PD == 1 || PD == 2, "prefetch depth");
   static constexpr int BX = 128;
   static constexpr int BY = W * RPW;
-  // restriction: coarse columns / rows per tile; norm, refinement: fine output per tile
-  static constexpr int CX = 62, CY = BY / 2 - 2;
-  static constexpr int OX = BX - 2, OY = BY - 2;
+  static constexpr int CX = 62, CY = BY / 2 - 2;  // coarse columns / rows per tile
   static_assert(RPW % 2 == 0, "fine row parity must be uniform across waves");
 
   struct Shared {
     T eu[2][W][2][2][64];  // edge rows of u: [buffer][wave][first/last row][column][lane]
     T ek[VAR ? 2 : 1][VAR ? W : 1][2][2][64];
-    // restriction: x-filtered residual of a wave's last row
-    T erx[2][MODE == kRestrict ? W : 1][64];
-    double red[W];
+    T erx[2][W][64];  // x-filtered residual of a wave's last row
   };
 
   struct Args {
     const T* f;
     const T* u;
     const T* k;
-    T* out;              // restriction: fc; refinement: u_out
-    const float* e;      // refinement: correction
-    float* r32;          // refinement: scaled residual
-    double* partial;     // norm, refinement
-    double scale;        // refinement: u_out = u + scale * e
-    double inv_scale;    // refinement: r32 = r * inv_scale
-    int zero_interior;   // norm: read the interior of u as 0
+    T* out;  // fc
     int n;
     T ih2;
     int tiles_x, tiles_y, zlen;
@@ -96,57 +88,37 @@ struct Stream {
     const int t = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + jb;
     const int tx = t % a.tiles_x, ty = (t / a.tiles_x) % a.tiles_y, tz = t / (a.tiles_x * a.tiles_y);
 
-    int gx0, gy0, sbeg, send;  // fine tile origin, residual planes [sbeg, send]
-    int Z0 = 0, Z1 = 0;
-    if (MODE == kRestrict) {
-      const int nc = (n - 1) / 2 + 1;
-      const int X0 = 1 + tx * CX, Y0 = 1 + ty * CY;
-      Z0 = 1 + tz * a.zlen;
-      Z1 = min(Z0 + a.zlen, nc - 1);
-      gx0 = 2 * X0 - 2;
-      gy0 = 2 * Y0 - 2;
-      sbeg = 2 * Z0 - 1;
-      send = 2 * Z1 - 1;
-    } else {
-      gx0 = tx * OX;  // owned columns: tile columns 1..BX-2
-      gy0 = ty * OY;
-      const int z0 = 1 + tz * a.zlen;
-      sbeg = z0;
-      send = min(z0 + a.zlen, n - 1) - 1;
-    }
+    // fine tile origin and residual planes [sbeg, send] of the coarse planes [Z0, Z1)
+    const int nc = (n - 1) / 2 + 1;
+    const int X0 = 1 + tx * CX, Y0 = 1 + ty * CY;
+    const int Z0 = 1 + tz * a.zlen;
+    const int Z1 = min(Z0 + a.zlen, nc - 1);
+    const int gx0 = 2 * X0 - 2, gy0 = 2 * Y0 - 2;
+    const int sbeg = 2 * Z0 - 1, send = 2 * Z1 - 1;
     const int gxa = gx0 + 2 * lane;
     const int gyw = gy0 + w * RPW;
 
     // Addresses: per-plane buffer resources, a uniform row byte offset and a per-lane
-    // column byte offset (for arrays of T and, in the refinement pass, of float).  Clamped
-    // coordinates keep every load in bounds.  Store offsets of columns this tile does not
-    // own are out of the plane's range, so those stores are dropped.
-    uint32_t cxb[2], sxb[2], cxf[2], sxf[2];
-    bool colin[2], colown[2];
+    // column byte offset.  Clamped coordinates keep every load in bounds.
+    uint32_t cxb[2];
+    bool colin[2];
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
-      const int gx = gxa + o, px = 2 * lane + o;
+      const int gx = gxa + o;
       const uint32_t c = (uint32_t)min(max(gx, 0), n - 1);
       colin[o] = gx >= 1 && gx <= n - 2;
-      colown[o] = colin[o] && px >= 1 && px <= BX - 2;
       cxb[o] = c * (uint32_t)sizeof(T);
-      sxb[o] = colown[o] ? cxb[o] : 0x80000000u;
-      cxf[o] = c * 4u;
-      sxf[o] = colown[o] ? cxf[o] : 0x80000000u;
     }
-    uint32_t rowb[RPW], rowf[RPW];
-    bool rowin[RPW], rowown[RPW];
+    uint32_t rowb[RPW];
+    bool rowin[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
-      const int gy = gyw + i, pr = w * RPW + i;
+      const int gy = gyw + i;
       const uint32_t r = (uint32_t)(min(max(gy, 0), n - 1) * n);
       rowb[i] = r * (uint32_t)sizeof(T);
-      rowf[i] = r * 4u;
       rowin[i] = gy >= 1 && gy <= n - 2;
-      rowown[i] = rowin[i] && pr >= 1 && pr <= BY - 2;
     }
     const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * sizeof(T));
-    const uint32_t planef = (uint32_t)((size_t)n * (size_t)n * 4u);
     const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;  // adjacent waves
 
     // Queue of the planes s-1, s, s+1 and PD prefetch buffers.  PD = 2: at step s the
@@ -155,7 +127,6 @@ struct Stream {
     // registers): plane s+2 is loaded and consumed in step s.
     T U[3][RPW][2], F[3][RPW][2], K[3][RPW][2];
     T PU[PD][RPW][2], PF[PD][RPW][2], PK[PD][RPW][2];
-    float PE[PD][RPW][2];
     auto load = [&](auto BC, int z) {
       constexpr int bb = decltype(BC)::value;
       const size_t zc = (size_t)min(max(z, 0), n - 1);
@@ -175,34 +146,15 @@ struct Stream {
 #pragma unroll
           for (int o = 0; o < 2; ++o) PK[bb][i][o] = buf_load<T>(bk, cxb[o], rowb[i]);
       }
-      // e == nullptr: no correction to apply (the first pass of a solve)
-      if constexpr (MODE == kRefine) {
-        if (a.e != nullptr) {
-          const PlaneBuf be = plane_buf(a.e, zc * planef, planef);
-#pragma unroll
-          for (int i = 0; i < RPW; ++i)
-#pragma unroll
-            for (int o = 0; o < 2; ++o) PE[bb][i][o] = buf_load<float>(be, cxf[o], rowf[i]);
-        }
-      }
     };
-    // Plane z enters the queue from buffer BB: norm with zero_interior reads the interior
-    // of u as 0; the refinement pass applies u + s e on interior nodes.
-    auto shift_in = [&](auto BC, int z) {
+    // plane z enters the queue from buffer BB
+    auto shift_in = [&](auto BC, int) {
       constexpr int bb = decltype(BC)::value;
-      const bool zin = z >= 1 && z <= n - 2;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          T v = PU[bb][i][o];
-          const bool in = zin && rowin[i] && colin[o];
-          if constexpr (MODE == kNorm) {
-            if (a.zero_interior && in) v = T(0);
-          }
-          if constexpr (MODE == kRefine) {
-            if (a.e != nullptr && in) v = v + (T)a.scale * (T)PE[bb][i][o];
-          }
+          const T v = PU[bb][i][o];
           U[0][i][o] = U[1][i][o]; U[1][i][o] = U[2][i][o]; U[2][i][o] = v;
           F[0][i][o] = F[1][i][o]; F[1][i][o] = F[2][i][o]; F[2][i][o] = PF[bb][i][o];
           if constexpr (VAR) {
@@ -240,27 +192,6 @@ struct Stream {
     for (int i = 0; i < RPW; ++i) rxprev[i] = T(0);
 #pragma unroll
     for (int i = 0; i < RPW / 2; ++i) acc[i] = T(0);
-    double sumsq = 0.0;
-
-    // Refinement pass: the results of plane sp are stored one step later (u_out from queue
-    // slot 0, r32 kept in RK), just before the next loads, so that the stores complete in
-    // the shadow of those loads instead of delaying the wait for them.
-    float RK[RPW][2];
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) RK[i][0] = RK[i][1] = 0.0f;
-    auto store_refined = [&](int sp) {
-      const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
-      const PlaneBuf br = plane_buf(a.r32, (size_t)sp * planef, planef);
-#pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        if (!rowown[i]) continue;
-#pragma unroll
-        for (int o = 0; o < 2; ++o) {
-          buf_store(U[0][i][o], bo, sxb[o], rowb[i]);
-          buf_store(RK[i][o], br, sxf[o], rowf[i]);
-        }
-      }
-    };
 
     // One step at plane s; the step's parity BB (step count from sbeg) selects the
     // prefetch buffer and the LDS edge buffers.
@@ -268,12 +199,11 @@ struct Stream {
       constexpr int bb = decltype(BC)::value;
       constexpr int rb = 1 - bb, wb = bb;  // LDS buffer written in the previous / this step
       __syncthreads();
-      if (MODE == kRefine && s > sbeg) store_refined(s - 1);
       constexpr int lb = PD == 2 ? 1 - bb : 0;  // buffer of this step's loads
       constexpr int cb = PD == 2 ? bb : 0;      // buffer of the plane entering the queue
       if (s + PD + 1 <= lastload) load(IC<lb>{}, s + PD + 1);
 
-      if (MODE == kRestrict && s > sbeg) {
+      if (s > sbeg) {
         // FW_y of plane s-1 for the coarse rows at even fine rows, then FW_z over the fine
         // planes 2Z-1 (1/4), 2Z (1/2), 2Z+1 (1/4)
         const int sp = s - 1;
@@ -349,56 +279,30 @@ struct Stream {
             r[i][o] = F[1][i][o] - au;
           }
         }
+        // fine nodes outside the interior carry no residual
         const bool zin = s >= 1 && s <= n - 2;
-        if constexpr (MODE == kRestrict) {
-          // fine nodes outside the interior carry no residual
 #pragma unroll
-          for (int i = 0; i < RPW; ++i) {
+        for (int i = 0; i < RPW; ++i) {
 #pragma unroll
-            for (int o = 0; o < 2; ++o)
-              r[i][o] = (zin && rowin[i] && colin[o]) ? r[i][o] : T(0);
-            const T left = from_lane_below(r[i][1]);
-            rxprev[i] = (T(0.25) * left + T(0.5) * r[i][0]) + T(0.25) * r[i][1];
-          }
-          sh.erx[wb][w][lane] = rxprev[RPW - 1];
-        } else {
-#pragma unroll
-          for (int i = 0; i < RPW; ++i)
-#pragma unroll
-            for (int o = 0; o < 2; ++o) {
-              if (!(zin && rowown[i] && colown[o])) continue;
-              const double rv = (double)r[i][o];
-              sumsq += rv * rv;
-              if constexpr (MODE == kRefine) RK[i][o] = (float)(rv * a.inv_scale);
-            }
+          for (int o = 0; o < 2; ++o)
+            r[i][o] = (zin && rowin[i] && colin[o]) ? r[i][o] : T(0);
+          const T left = from_lane_below(r[i][1]);
+          rxprev[i] = (T(0.25) * left + T(0.5) * r[i][0]) + T(0.25) * r[i][1];
         }
+        sh.erx[wb][w][lane] = rxprev[RPW - 1];
       }
       // next step: planes s, s+1, s+2; edges of plane s+1 (slot 2 before the shift)
       write_edges(wb, 2);
       shift_in(IC<cb>{}, s + 2);
     };
 
-    const int last = MODE == kRestrict ? send + 1 : send;
+    // one step past the last residual plane: its FW_y and FW_z complete the last coarse plane
+    const int last = send + 1;
     for (int s = sbeg; s <= last;) {
       stepfn(IC<0>{}, s);
       if (++s > last) break;
       stepfn(IC<1>{}, s);
       ++s;
-    }
-    // the last plane (now in queue slot 0)
-    if (MODE == kRefine) store_refined(send);
-
-    if (MODE != kRestrict) {
-#pragma unroll
-      for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
-      __syncthreads();
-      if (lane == 0) sh.red[w] = sumsq;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int v = 0; v < W; ++v) tot += sh.red[v];
-        a.partial[blockIdx.x] = tot;
-      }
     }
   }
 };
