@@ -49,7 +49,16 @@ struct mg_ctx {
   bool coeffs = false;
   int fuse = MG_FUSE_ALL;  // kernel-fusion flags (mg_set_fusion)
   int tail_first = -1;  // first level handled by the one-launch coarse tail (-1: none)
+  // norm read-back without draining the stream: a pinned host word and an event after the
+  // copy (nullptr: synchronous reads only)
+  double* hnorm = nullptr;
+  hipEvent_t ev = nullptr;
   char err[512] = "no error";
+  ~mg_ctx()
+  {
+    if (ev) (void)hipEventDestroy(ev);
+    if (hnorm) (void)hipHostFree(hnorm);
+  }
 };
 
 namespace {
@@ -354,11 +363,34 @@ mg_status finish(mg_ctx* c, int k, double rel, double tol, int* cycles, double* 
   return MG_OK;
 }
 
+// Enqueues the copy of the device scalar *dev to the pinned host word and the event after it.
+mg_status read_scalar_start(mg_ctx* c, const double* dev)
+{
+  mg_status st = hip_check(c, hipMemcpyAsync(c->hnorm, dev, sizeof(double), hipMemcpyDeviceToHost, c->s),
+                           "reading a norm");
+  if (!st) st = hip_check(c, hipEventRecord(c->ev, c->s), "recording the norm event");
+  return st;
+}
+
+mg_status read_scalar_finish(mg_ctx* c, double* host)
+{
+  if (mg_status st = hip_check(c, hipEventSynchronize(c->ev), "waiting for a norm")) return st;
+  *host = *c->hnorm;
+  return MG_OK;
+}
+
 // Refinement on a large 3D grid with the fused pass (mg_resid_tiled.hip): every pass
 // applies the previous FP32 correction, forms the FP64 residual, its norm and the scaled
 // FP32 right-hand side of the next cycle, writing the updated iterate out of place (u and
 // the level's second buffer alternate).  The scale of a pass's r32 is a power of two taken
 // from the previous residual norm; powers of two change no float result.
+//
+// Norm read-back overlaps the next FP32 V-cycle: when the contraction observed so far says
+// the norm being read will still be above the tolerance, the next cycle (which writes only
+// the FP32 correction and the coarse levels, never the iterate or r32) is enqueued before
+// the host waits for the norm.  If the tolerance was reached after all, that cycle's
+// results are never used: the iterate, the cycle count and the stopping decision are those
+// of the plain loop, only GPU time is lost.
 mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, double bn,
                             int* cycles, double* relres)
 {
@@ -367,15 +399,30 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
   double* other = L0.t;
   double scale = ir_scale(c, bn);  // scale of the r32 being written
   double rn2 = 0;
+  const bool overlap = c->hnorm != nullptr && c->ev != nullptr;
   mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other, L0.f32,
                      c->partial, c->scal);
   std::swap(cur, other);
   mg_status st = launch_check(c, "refinement pass");
-  if (!st) st = read_scalar(c, c->scal, &rn2);
+  // relative residual predicted for the norm in flight (infinite: no history yet)
+  double predicted = INFINITY, rel_prev = NAN;
+  float* spec = nullptr;  // a V-cycle enqueued ahead of the norm read
+  auto read_norm = [&]() -> mg_status {
+    if (!overlap) return read_scalar(c, c->scal, &rn2);
+    mg_status s2 = read_scalar_start(c, c->scal);
+    if (!s2 && predicted > 4.0 * tol && c->g.max_cycles > 0) {
+      spec = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+      s2 = launch_check(c, "V-cycle");
+    }
+    if (!s2) s2 = read_scalar_finish(c, &rn2);
+    return s2;
+  };
+  if (!st) st = read_norm();
   double rel = std::sqrt(rn2) / bn;
   int k = 0;
   while (!st && std::isfinite(rel) && rel > tol && k < c->g.max_cycles) {
-    float* e = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+    float* e = spec ? spec : cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+    spec = nullptr;
     const double next = ir_scale(c, std::sqrt(rn2));
     mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, e, scale, 1.0 / next, other, L0.f32,
                        c->partial, c->scal);
@@ -383,7 +430,11 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
     scale = next;
     ++k;
     if ((st = launch_check(c, "refinement pass"))) break;
-    if ((st = read_scalar(c, c->scal, &rn2))) break;
+    // contraction so far: the next relative residual is about rel * (rel / rel_prev)
+    const double rho = std::isfinite(rel_prev) && rel_prev > 0 ? rel / rel_prev : 1.0;
+    predicted = k < c->g.max_cycles ? rel * rho : 0.0;
+    rel_prev = rel;
+    if ((st = read_norm())) break;
     rel = std::sqrt(rn2) / bn;
   }
   if (cur != u) mgk::copy<double>(c->s, L0.N, cur, u);
@@ -503,6 +554,16 @@ mg_status mg_setup(const mg_grid* grid, void* workspace, size_t bytes, void* str
   if (!grid->variable) {
     const Level& Lc = c->lv[grid->levels - 1];
     mgk::coarsest_factor(c->s, grid->dim, Lc.n, Lc.h, nullptr, c->chol, c->ainv, c->flag);
+  }
+  // one pinned host word for overlapped norm reads (FP32 refinement); without it the solve
+  // reads synchronously
+  if (grid->precision == MG_F32_IR) {
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, 64, hipHostMallocDefault) == hipSuccess) {
+      c->hnorm = static_cast<double*>(hp);
+      if (hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) c->ev = nullptr;
+    }
+    (void)hipGetLastError();  // a failed pinned allocation only disables the overlap
   }
   if (mg_status st = launch_check(c, "setup")) {
     snprintf(g_err, sizeof g_err, "%s", c->err);
