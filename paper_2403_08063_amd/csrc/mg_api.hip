@@ -45,7 +45,9 @@ struct mg_ctx {
   double* ainv = nullptr;
   int* flag = nullptr;
   double* partial = nullptr;
+  double* partial_b = nullptr;  // second partial sums (right-hand-side norm of the first pass)
   double* scal = nullptr;  // device scalars: [0] norm2, [1] rhs norm2
+  double last_bn = 0.0;    // right-hand-side norm of the previous solve (0: none)
   bool coeffs = false;
   int fuse = MG_FUSE_ALL;  // kernel-fusion flags (mg_set_fusion)
   int tail_first = -1;  // first level handled by the one-launch coarse tail (-1: none)
@@ -145,6 +147,7 @@ void layout(const mg_grid* g, Carver& cv, mg_ctx* c)
   double* chol = cv.take<double>((size_t)m * m);
   double* ainv = cv.take<double>((size_t)m * m);
   double* partial = cv.take<double>(mgk::kStreamPartials);
+  double* partial_b = cv.take<double>(mgk::kStreamPartials);
   double* scal = cv.take<double>(8);
   int* flag = cv.take<int>(4);
   if (c) {
@@ -152,6 +155,7 @@ void layout(const mg_grid* g, Carver& cv, mg_ctx* c)
     c->chol = chol;
     c->ainv = ainv;
     c->partial = partial;
+    c->partial_b = partial_b;
     c->scal = scal;
     c->flag = flag;
   }
@@ -363,19 +367,19 @@ mg_status finish(mg_ctx* c, int k, double rel, double tol, int* cycles, double* 
   return MG_OK;
 }
 
-// Enqueues the copy of the device scalar *dev to the pinned host word and the event after it.
-mg_status read_scalar_start(mg_ctx* c, const double* dev)
+// Enqueues the copy of `count` device scalars to the pinned host words and the event after it.
+mg_status read_scalar_start(mg_ctx* c, const double* dev, int count = 1)
 {
-  mg_status st = hip_check(c, hipMemcpyAsync(c->hnorm, dev, sizeof(double), hipMemcpyDeviceToHost, c->s),
-                           "reading a norm");
+  mg_status st = hip_check(c, hipMemcpyAsync(c->hnorm, dev, count * sizeof(double),
+                                             hipMemcpyDeviceToHost, c->s), "reading a norm");
   if (!st) st = hip_check(c, hipEventRecord(c->ev, c->s), "recording the norm event");
   return st;
 }
 
-mg_status read_scalar_finish(mg_ctx* c, double* host)
+mg_status read_scalar_finish(mg_ctx* c, double* host, int count = 1)
 {
   if (mg_status st = hip_check(c, hipEventSynchronize(c->ev), "waiting for a norm")) return st;
-  *host = *c->hnorm;
+  for (int i = 0; i < count; ++i) host[i] = c->hnorm[i];
   return MG_OK;
 }
 
@@ -391,33 +395,68 @@ mg_status read_scalar_finish(mg_ctx* c, double* host)
 // the host waits for the norm.  If the tolerance was reached after all, that cycle's
 // results are never used: the iterate, the cycle count and the stopping decision are those
 // of the plain loop, only GPU time is lost.
+//
+// bn: the right-hand-side norm, or 0 to have the first pass compute it beside the residual
+// norm (same operations and summation order as the separate norm pass); that pass then
+// scales r32 by the previous solve's right-hand side and is repeated with the right scale
+// in the rare case that this is more than 2^40 off (powers of two within that range change
+// no float result).
 mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, double bn,
                             int* cycles, double* relres)
 {
   Level& L0 = c->lv[0];
   double* cur = u;
   double* other = L0.t;
-  double scale = ir_scale(c, bn);  // scale of the r32 being written
+  const bool fused_rhs = !(bn > 0);
+  double scale = ir_scale(c, fused_rhs ? c->last_bn : bn);  // scale of the r32 being written
   double rn2 = 0;
   const bool overlap = c->hnorm != nullptr && c->ev != nullptr;
   mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other, L0.f32,
-                     c->partial, c->scal);
+                     c->partial, c->scal, fused_rhs ? c->partial_b : nullptr);
   std::swap(cur, other);
   mg_status st = launch_check(c, "refinement pass");
   // relative residual predicted for the norm in flight (infinite: no history yet)
   double predicted = INFINITY, rel_prev = NAN;
   float* spec = nullptr;  // a V-cycle enqueued ahead of the norm read
-  auto read_norm = [&]() -> mg_status {
-    if (!overlap) return read_scalar(c, c->scal, &rn2);
-    mg_status s2 = read_scalar_start(c, c->scal);
+  // reads `count` norms from scal (residual, then right-hand side), overlapping the next
+  // V-cycle when the prediction says one is needed
+  auto read_norm = [&](double* out, int count) -> mg_status {
+    if (!overlap) {
+      mg_status s2 = MG_OK;
+      for (int i = 0; i < count && !s2; ++i) s2 = read_scalar(c, c->scal + i, &out[i]);
+      return s2;
+    }
+    mg_status s2 = read_scalar_start(c, c->scal, count);
     if (!s2 && predicted > 4.0 * tol && c->g.max_cycles > 0) {
       spec = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
       s2 = launch_check(c, "V-cycle");
     }
-    if (!s2) s2 = read_scalar_finish(c, &rn2);
+    if (!s2) s2 = read_scalar_finish(c, out, count);
     return s2;
   };
-  if (!st) st = read_norm();
+  if (!st && fused_rhs) {
+    double two[2] = {0, 0};
+    st = read_norm(two, 2);
+    rn2 = two[0];
+    bn = std::sqrt(two[1]);
+    if (!(bn > 0)) bn = 1.0;
+    const double ideal = ir_scale(c, bn);
+    if (!st && (ideal / scale > 0x1p40 || scale / ideal > 0x1p40)) {
+      // redo the first pass with the right scale (its r32 feeds the first cycle: a cycle
+      // enqueued ahead is discarded)
+      spec = nullptr;
+      std::swap(cur, other);
+      scale = ideal;
+      mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other,
+                         L0.f32, c->partial, c->scal);
+      std::swap(cur, other);
+      st = launch_check(c, "refinement pass");
+      if (!st) st = read_norm(&rn2, 1);
+    }
+  } else if (!st) {
+    st = read_norm(&rn2, 1);
+  }
+  c->last_bn = bn;
   double rel = std::sqrt(rn2) / bn;
   int k = 0;
   while (!st && std::isfinite(rel) && rel > tol && k < c->g.max_cycles) {
@@ -434,7 +473,7 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
     const double rho = std::isfinite(rel_prev) && rel_prev > 0 ? rel / rel_prev : 1.0;
     predicted = k < c->g.max_cycles ? rel * rho : 0.0;
     rel_prev = rel;
-    if ((st = read_norm())) break;
+    if ((st = read_norm(&rn2, 1))) break;
     rel = std::sqrt(rn2) / bn;
   }
   if (cur != u) mgk::copy<double>(c->s, L0.N, cur, u);
@@ -450,6 +489,10 @@ mg_status solve_impl(mg_ctx* c, const double* f, double* u, double tol, int* cyc
   if (!(tol > 0) || !std::isfinite(tol)) return fail(c, MG_EINVAL, "tol must be > 0");
   Level& L0 = c->lv[0];
   if (use_tiled(c, 0)) mgk::copy_boundary(c->s, c->g.dim, L0.n, u, L0.t);
+  // FP32 refinement with the fused pass: once a previous solve gave a right-hand-side
+  // scale, the first pass computes the right-hand-side norm itself
+  if (c->g.precision == MG_F32_IR && use_tiled(c, 0) && !c->g.variable && c->last_bn > 0)
+    return solve_ir_streamed(c, f, u, tol, 0.0, cycles, relres);
   double bn2 = 0, rn2 = 0;
   norm2(c, f, u, 1, 1);
   if (mg_status st = launch_check(c, "norm")) return st;

@@ -55,9 +55,12 @@ void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const do
                        const double* u, int mode, double* partial, double* out);
 // Refinement pass: uout = u + scale * e on interior nodes (boundary of uout not written),
 // r = f - A uout, r32 = (float)(r * inv_scale), out[0] = sum of r^2 (interior).
+// partial_b (constant coefficient, e == nullptr: the first pass of a solve): also out[1] =
+// the sum of squares of the full right-hand side f - A u_B (interior of u read as 0), equal
+// to resid_norm2_tiled's mode 1 (same tiles and summation order); kStreamPartials doubles.
 void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
                    const double* u, const float* e, double scale, double inv_scale, double* uout,
-                   float* r32, double* partial, double* out);
+                   float* r32, double* partial, double* out, double* partial_b = nullptr);
 
 // u += P ec on fine interior nodes (nc = coarse nodes per side).
 template <typename T>

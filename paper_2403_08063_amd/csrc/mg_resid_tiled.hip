@@ -36,7 +36,8 @@ namespace {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4, kFvRestrict = 5 };
+enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4, kFvRestrict = 5,
+       kRefineRhs = 6 };
 
 // (A u)_i of the cell-centred finite-volume operator from the six neighbour values (ghost
 // neighbours already replaced by 2 g - u_i), in the order -x, +x, -y, +y, -z, +z.
@@ -333,6 +334,11 @@ struct Stream {
 template <bool VAR, int MODE, int W, int RPW, int CP>
 struct Pass {
   static constexpr bool FV = MODE == kFvNorm || MODE == kFvJacobi || MODE == kFvRestrict;
+  // refinement pass; kRefineRhs (the first pass of a solve, no correction) also sums the
+  // squares of the full right-hand side b = f - A u_B (u_B: the Dirichlet data of u with a
+  // zero interior), with the operations of the norm pass reading the interior of u as 0
+  static constexpr bool REFINE = MODE == kRefine || MODE == kRefineRhs;
+  static constexpr bool RHS = MODE == kRefineRhs;
   static_assert(MODE != kFvRestrict || RPW % 2 == 0, "row pairs of the restriction");
   static_assert(!(FV && VAR), "the finite-volume scheme has a constant coefficient");
   static_assert(W >= 2, "the first and the last wave load the tile's halo rows");
@@ -343,6 +349,7 @@ struct Pass {
     double eu[2][W][NE][CP][2][64];  // [buffer][wave][first/last row][pair][column][lane]
     double ek[VAR ? 2 : 1][VAR ? W : 1][VAR ? NE : 1][VAR ? CP : 1][2][64];
     double red[W];
+    double redb[W];
   };
 
   struct Args {
@@ -360,6 +367,7 @@ struct Pass {
     int n;
     double ih2;
     int tiles_x, tiles_y, zlen;
+    double* partial_b;   // kRefineRhs: per-workgroup sums of b^2
   };
 
   __device__ __forceinline__ static void run(const Args& a, Shared& sh)
@@ -411,7 +419,7 @@ struct Pass {
     const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * 8u);
     const uint32_t planef = (uint32_t)((size_t)n * (size_t)n * 4u);
     const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;
-    const bool corr = MODE == kRefine && a.e != nullptr;
+    const bool corr = REFINE && a.e != nullptr;
     // finite volumes: which neighbours of a lane's cells are ghost cells (x per pair and
     // column, y per row; z per plane in the step)
     bool gx0[CP], gxp0[CP], gxp1[CP], gym[RPW], gyp[RPW];
@@ -562,7 +570,7 @@ struct Pass {
       const int c = ox + 128 * p + 2 * lane;
       cco[p] = in0[p] ? (uint32_t)((c + 1) / 2) * 8u : 0x80000000u;
     }
-    double sumsq = 0.0;
+    double sumsq = 0.0, sumsq_b = 0.0;
     auto store = [&](int sp) {  // u_out from queue slot 0, r32 from RK
       const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
       if constexpr (MODE == kFvJacobi) {
@@ -602,7 +610,7 @@ struct Pass {
       constexpr int bb = decltype(BC)::value;
       constexpr int rb = 1 - bb, wb = bb;  // LDS buffer written in the previous / this step
       __syncthreads();
-      if ((MODE == kRefine || MODE == kFvJacobi) && s > z0) store(s - 1);
+      if ((REFINE || MODE == kFvJacobi) && s > z0) store(s - 1);
       const bool gzm = s == 1, gzp = s + 1 == n - 1;
       if (s + 2 <= z1) load_q(s + 2);
       if (s + 1 < z1) load_c(s + 1);
@@ -661,7 +669,19 @@ struct Pass {
             const double r = F[i][p][o] - au;
             const bool own = rin[i] && (o ? in1[p] : in0[p]);
             if (own) sumsq += r * r;
-            if constexpr (MODE == kRefine) RK[i][p][o] = own ? (float)(r * a.inv_scale) : 0.0f;
+            if constexpr (RHS) {
+              // interior neighbours (and the owned node itself) read as 0
+              const int c = ox + 128 * p + 2 * lane + o, gy = oy + w * RPW + i;
+              const bool ixm = c - 1 >= 1, ixp = c + 1 <= n - 2;
+              const bool iym = gy - 1 >= 1, iyp = gy + 1 <= n - 2;
+              const bool izm = s - 1 >= 1, izp = s + 1 <= n - 2;
+              const double bau = au_const<double, 3>(a.ih2, 0.0, ixm ? 0.0 : xm, ixp ? 0.0 : xp,
+                                                     iym ? 0.0 : ym, iyp ? 0.0 : yp,
+                                                     izm ? 0.0 : zm, izp ? 0.0 : zp);
+              const double bv = F[i][p][o] - bau;
+              if (own) sumsq_b += bv * bv;
+            }
+            if constexpr (REFINE) RK[i][p][o] = own ? (float)(r * a.inv_scale) : 0.0f;
             if constexpr (MODE == kFvJacobi) JV[i][p][o] = ui + a.coef * r;
             if constexpr (MODE == kFvRestrict) {
               // steps of parity 0 are the odd (first) planes of a coarse cell's children
@@ -695,18 +715,28 @@ struct Pass {
       stepfn(IC<1>{}, s);
       ++s;
     }
-    if (MODE == kRefine || MODE == kFvJacobi) store(z1 - 1);  // queue slot 0 holds plane z1-1
+    if (REFINE || MODE == kFvJacobi) store(z1 - 1);  // queue slot 0 holds plane z1-1
     if constexpr (MODE == kFvJacobi || MODE == kFvRestrict) return;  // no norm
 
 #pragma unroll
     for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
+    if constexpr (RHS) {
+#pragma unroll
+      for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq_b += __shfl_xor(sumsq_b, o2, 64);
+    }
     __syncthreads();
     if (lane == 0) sh.red[w] = sumsq;
+    if (RHS && lane == 0) sh.redb[w] = sumsq_b;
     __syncthreads();
     if (threadIdx.x == 0) {
       double tot = 0.0;
       for (int v = 0; v < W; ++v) tot += sh.red[v];
       a.partial[blockIdx.x] = tot;
+      if constexpr (RHS) {
+        double totb = 0.0;
+        for (int v = 0; v < W; ++v) totb += sh.redb[v];
+        a.partial_b[blockIdx.x] = totb;
+      }
     }
   }
 };
@@ -870,11 +900,16 @@ void launch_pass(hipStream_t s, typename Pass<VAR, MODE, W, RPW, CP>::Args a, do
   a.tiles_x = (m + C::BX - 1) / C::BX;
   a.tiles_y = (m + C::BY - 1) / C::BY;
   const int per = a.tiles_x * a.tiles_y;
-  a.zlen = best_zlen(per, m, 2, capacity_of(kern, 64 * W), kStreamPartials);
+  // the first refinement pass takes the norm pass's z-chunks, so that its right-hand-side
+  // norm is summed in the norm pass's order
+  const int cap = MODE == kRefineRhs ? capacity_of(k_pass<VAR, kNorm, W, RPW, CP>, 64 * W)
+                                     : capacity_of(kern, 64 * W);
+  a.zlen = best_zlen(per, m, 2, cap, kStreamPartials);
   const int blocks = per * ((m + a.zlen - 1) / a.zlen);
   a.partial = partial;
   kern<<<blocks, 64 * W, 0, s>>>(a);
   k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
+  if (MODE == kRefineRhs) k_sum_fixed<<<1, 256, 0, s>>>(a.partial_b, blocks, out + 1);
 }
 
 template <bool VAR, int MODE>
@@ -914,13 +949,17 @@ void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const do
 
 void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
                    const double* u, const float* e, double scale, double inv_scale, double* uout,
-                   float* r32, double* partial, double* out)
+                   float* r32, double* partial, double* out, double* partial_b)
 {
   auto fill = [&](auto& a) {
     a.f = f; a.u = u; a.k = k; a.n = n; a.ih2 = 1.0 / (h * h); a.e = e; a.scale = scale;
-    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32;
+    a.inv_scale = inv_scale; a.out = uout; a.r32 = r32; a.partial_b = partial_b;
   };
-  if (k) {
+  if (!k && partial_b && !e) {
+    Pass<false, kRefineRhs, 4, 2, 4>::Args a{};
+    fill(a);
+    run_pass<false, kRefineRhs>(s, a, partial, out);
+  } else if (k) {
     Pass<true, kRefine, 4, 2, 4>::Args a{};
     fill(a);
     run_pass<true, kRefine>(s, a, partial, out);

@@ -331,6 +331,30 @@ def test_solves_are_deterministic():
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[2], outs[3])
 
 
+@pytest.mark.parametrize("n,levels", [(161, 6), (257, 7)])
+def test_repeated_fp32_refined_solves_fused_rhs_norm(n, levels):
+    """From the second solve on a context, the first refinement pass computes the
+    right-hand-side norm itself (with the previous solve's scale for r32): same cycles,
+    same relative residual, same solution bit for bit.  A right-hand side 2^50 times
+    larger forces the pass to be repeated with the right scale: the solution scales
+    exactly."""
+    say(f"fused rhs norm n={n}")
+    f = dev(inputs.uniform_interior(3, n, 13))
+    mg = Multigrid(3, n, levels, precision="f32_ir", device=DEV)
+    u1, i1 = mg.solve(f, tol=1e-10)
+    u1 = host(u1)
+    u2, i2 = mg.solve(f, tol=1e-10)
+    assert (i2.cycles, i2.relres) == (i1.cycles, i1.relres)
+    assert np.array_equal(host(u2), u1)
+    big = 2.0 ** 50
+    u3, i3 = mg.solve(f * big, tol=1e-10)
+    assert (i3.cycles, i3.relres) == (i1.cycles, i1.relres)
+    assert np.array_equal(host(u3), u1 * big)
+    u4, i4 = mg.solve(f, tol=1e-10)  # back from the large scale
+    assert np.array_equal(host(u4), u1)
+    mg.close()
+
+
 # ---------------------------------------------------------------- adjoint and gradient
 def test_gradient_pass_matches_oracle(oracle):
     n = 65
