@@ -112,6 +112,39 @@ std::vector<int> build_faces(const std::vector<BlockDesc>& blocks)
   return t;
 }
 
+// Lagrange weights of `cnt` bases at `nodes` for target x (host: the C2F weight table)
+void lagrange(int cnt, const double* nodes, double x, double* w)
+{
+  for (int i = 0; i < cnt; ++i) {
+    double v = 1.0;
+    for (int j = 0; j < cnt; ++j)
+      if (j != i) v *= (x - nodes[j]) / (nodes[i] - nodes[j]);
+    w[i] = v;
+  }
+}
+
+// C2F weights: along the normal (bases 0, -1, -2 away from the face, target +1/4) and along
+// a tangential axis for each choice of the first base (-2, -1, 0) and target (-1/4, +1/4)
+struct C2FWeights {
+  double wn[3];
+  double wt[3][2][3];  // [first base + 2][target: 0 = -1/4, 1 = +1/4][base]
+};
+
+C2FWeights c2f_weights(int order)
+{
+  C2FWeights W{};
+  const int cnt = order + 1;
+  double nodes[3];
+  for (int a = 0; a < cnt; ++a) nodes[a] = -(double)a;
+  lagrange(cnt, nodes, 0.25, W.wn);
+  for (int first = -2; first <= 0; ++first)
+    for (int t = 0; t < 2; ++t) {
+      for (int a = 0; a < cnt; ++a) nodes[a] = first + a;
+      lagrange(cnt, nodes, t ? 0.25 : -0.25, W.wt[first + 2][t]);
+    }
+  return W;
+}
+
 }  // namespace
 
 struct mgblk_ctx {
@@ -124,6 +157,7 @@ struct mgblk_ctx {
   double* scal = nullptr;
   size_t cnt = 0;         // doubles of all blocks
   std::vector<double> hhost;
+  C2FWeights w{};
   char err[512] = "no error";
 };
 
@@ -201,45 +235,26 @@ __device__ __forceinline__ void face_coords(int ax, int n, int t1, int t2, int& 
   else { z = n; x = t1; y = t2; }
 }
 
-// Lagrange weights of `cnt` bases at `nodes` for target x
-__device__ __forceinline__ void lagrange(int cnt, const double* nodes, double x, double* w)
+// first tangential base (offset from coarse index T, 0-based in [0, B)) for the fine position
+// on side t (0: -1/4, 1: +1/4)
+__device__ __forceinline__ int tangential_first(int order, int T, int B, int t)
 {
-  for (int i = 0; i < cnt; ++i) {
-    double v = 1.0;
-    for (int j = 0; j < cnt; ++j)
-      if (j != i) v *= (x - nodes[j]) / (nodes[i] - nodes[j]);
-    w[i] = v;
-  }
-}
-
-// tangential bases (offsets from coarse index T, 0-based in [0, B)) for target -1/4 or +1/4
-__device__ __forceinline__ int tangential_nodes(int order, int T, int B, double target, double* nodes)
-{
-  if (order == 0) {
-    nodes[0] = 0.0;
-    return 1;
-  }
+  if (order == 0) return 0;
   if (order == 1) {
-    double a = target < 0 ? -1.0 : 0.0;
-    if (T + (int)a < 0) a = 0.0;
-    if (T + (int)a + 1 >= B) a = -1.0;
-    nodes[0] = a;
-    nodes[1] = a + 1.0;
-    return 2;
+    int a = t ? 0 : -1;
+    if (T + a < 0) a = 0;
+    if (T + a + 1 >= B) a = -1;
+    return a;
   }
-  double a = -1.0;
-  if (T - 1 < 0) a = 0.0;          // the downwind base would be a ghost: remap by -2 o
-  else if (T + 1 >= B) a = -2.0;   // the upwind one
-  nodes[0] = a;
-  nodes[1] = a + 1.0;
-  nodes[2] = a + 2.0;
-  return 3;
+  if (T - 1 < 0) return 0;       // the downwind base would be a ghost: remap by -2 o
+  if (T + 1 >= B) return -2;     // the upwind one
+  return -1;
 }
 
 constexpr int kFillThreads = 256;
 
 __global__ void __launch_bounds__(kFillThreads)
-    k_blk_fill(int B, int order, const int* __restrict__ faces, double* __restrict__ u)
+    k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
 {
   const int m = B + 2;
   const int q = blockIdx.x * kFillThreads + threadIdx.x;  // ghost cell of the face
@@ -279,23 +294,19 @@ __global__ void __launch_bounds__(kFillThreads)
   // C2F: coarse cell (T1, T2) of the quadrant and the fine position in it
   const int cb = e[1];
   const int T1 = e[5] * half + (t1 - 1) / 2, T2 = e[6] * half + (t2 - 1) / 2;
-  const double x1 = ((t1 - 1) % 2 == 0) ? -0.25 : 0.25, x2 = ((t2 - 1) % 2 == 0) ? -0.25 : 0.25;
-  double nn[3], wn[3], n1[3], w1[3], n2[3], w2[3];
+  const int p1 = (t1 - 1) % 2, p2 = (t2 - 1) % 2;  // 0: -1/4, 1: +1/4
+  const int a1 = tangential_first(order, T1, B, p1), a2 = tangential_first(order, T2, B, p2);
+  const double* w1 = W.wt[a1 + 2][p1];
+  const double* w2 = W.wt[a2 + 2][p2];
   const int cn = order + 1;
-  for (int a = 0; a < cn; ++a) nn[a] = -(double)a;  // 0, -1, -2: away from the interface
-  lagrange(cn, nn, 0.25, wn);
-  const int c1 = tangential_nodes(order, T1, B, x1, n1);
-  const int c2 = tangential_nodes(order, T2, B, x2, n2);
-  lagrange(c1, n1, x1, w1);
-  lagrange(c2, n2, x2, w2);
   const int ci = side ? 1 : B, away = side ? 1 : -1;
   double s = 0.0;
-  for (int a = 0; a < cn; ++a)
-    for (int j2 = 0; j2 < c2; ++j2)
-      for (int j1 = 0; j1 < c1; ++j1) {
+  for (int a = 0; a < cn; ++a)  // normal bases 0, -1, -2: away from the interface
+    for (int j2 = 0; j2 < cn; ++j2)
+      for (int j1 = 0; j1 < cn; ++j1) {
         int x, y, z;
-        face_coords(ax, ci - away * (int)nn[a], T1 + 1 + (int)n1[j1], T2 + 1 + (int)n2[j2], x, y, z);
-        s += wn[a] * w2[j2] * w1[j1] * u[bidx(m, cb, z, y, x)];
+        face_coords(ax, ci + away * a, T1 + 1 + a1 + j1, T2 + 1 + a2 + j2, x, y, z);
+        s += W.wn[a] * w2[j2] * w1[j1] * u[bidx(m, cb, z, y, x)];
       }
   u[gi] = s;
 }
@@ -383,7 +394,7 @@ void fill(mgblk_ctx* c, double* u)
 {
   const int B = c->g.B;
   const dim3 grid((unsigned)((B * B + kFillThreads - 1) / kFillThreads), 6, kBlocks);
-  k_blk_fill<<<grid, kFillThreads, 0, c->s>>>(B, c->g.order, c->faces, u);
+  k_blk_fill<<<grid, kFillThreads, 0, c->s>>>(B, c->g.order, c->w, c->faces, u);
 }
 
 // sweeps with a fill before each, alternating u and the second buffer; returns the result
@@ -444,6 +455,7 @@ mg_status mgblk_setup(const mgblk_grid* grid, void* workspace, size_t bytes, voi
   if (!c) return blk_fail(nullptr, MG_ENOMEM, "host allocation of the context failed");
   c->g = *grid;
   c->s = static_cast<hipStream_t>(stream);
+  c->w = c2f_weights(grid->order);
   BlkCarver cv{static_cast<char*>(workspace)};
   blk_layout(grid, cv, c);
   const std::vector<BlockDesc> blocks = build_layout();
