@@ -21,6 +21,10 @@ axis: order 0 copies the coarse cell, order 1 uses the two nearest bases (the ad
 and the next one away from the interface along the normal; tangentially the cell and its
 neighbour on the fine cell's side, remapped to the other side at the block edge).
 
+The composite system is solved as in Sect. 5 by V(3,3)-cycles over levels of the same layout
+with B/2^l cells per block (damped Jacobi as smoother and coarse solver); the transfers the
+paper leaves open are stated with ``prolong_add`` and ``restrict`` below.
+
 Layout (Sect. 5: 56 blocks on level 2 and 64 on level 3): [0,1]^3 split into 4^3 level-2
 blocks of width 1/4, the central 2^3 refined into 8 level-3 blocks of width 1/8 each.  Each
 block has B^3 cells (its own h = width / B) and is stored as a (B+2)^3 array with a ghost
@@ -278,40 +282,71 @@ def cell_centres(B):
     return out
 
 
+def _boundary_faces():
+    """(nb, 3, 2) mask: face (axis x/y/z, side low/high) of each block on the domain boundary."""
+    blocks = layout()
+    faces = face_neighbours(blocks)
+    mask = np.zeros((len(blocks), 3, 2), dtype=bool)
+    for b, f in enumerate(faces):
+        for (ax, side), nb in f.items():
+            mask[b, ax, side] = nb[0] == "boundary"
+    return mask
+
+
+def block_h(B):
+    """(nb,) cell width h of every block: its width / B."""
+    return np.array([w / B for (_, _, w) in layout()])
+
+
+# (array slice of the neighbour, array axis of the block's (z, y, x) data) per face, in the
+# order -x, +x, -y, +y, -z, +z
+_NEIGHBOURS = (
+    ((0, 0), (slice(1, -1), slice(1, -1), slice(0, -2)), 2),
+    ((0, 1), (slice(1, -1), slice(1, -1), slice(2, None)), 2),
+    ((1, 0), (slice(1, -1), slice(0, -2), slice(1, -1)), 1),
+    ((1, 1), (slice(1, -1), slice(2, None), slice(1, -1)), 1),
+    ((2, 0), (slice(0, -2), slice(1, -1), slice(1, -1)), 0),
+    ((2, 1), (slice(2, None), slice(1, -1), slice(1, -1)), 0),
+)
+
+
+def apply_operator(arr, B):
+    """A u at the inner cells of every block, (nb, B, B, B), from the stored values as they are
+    (ghosts already filled): (1/h^2) sum over the six neighbours of (u_i - u_nb), a neighbour
+    in a domain-boundary ghost taken as 2 g - u_i."""
+    nb = len(layout())
+    m = B + 2
+    U = arr.reshape(nb, m, m, m)
+    c = U[:, 1:-1, 1:-1, 1:-1]
+    bnd = _boundary_faces()
+    s = None
+    for (ax, side), sl, arrax in _NEIGHBOURS:
+        v = U[(slice(None),) + sl].copy()
+        edge = [slice(None)] * 4
+        edge[1 + arrax] = 0 if side == 0 else -1
+        edge = tuple(edge)
+        on = bnd[:, ax, side][:, None, None]
+        v[edge] = np.where(on, 2.0 * v[edge] - c[edge], v[edge])
+        s = c - v if s is None else s + (c - v)
+    h = block_h(B)
+    return s * (1.0 / (h * h))[:, None, None, None]
+
+
 def jacobi_sweep(arr, f, B, order, omega=0.8, g=None):
     """One damped Jacobi sweep on every block (ghosts filled first from the current values):
     u_i <- u_i + omega (h^2/6) (f_i - A u_i), ghost neighbours on the domain boundary as
     2 g - u_i, the other ghost cells directly.  arr, f: concatenated block arrays."""
     fill(arr, B, order, g)
-    blocks = layout()
+    nb = len(layout())
     m = B + 2
     out = arr.copy()
-    U = arr.reshape(len(blocks), m, m, m)
-    F = f.reshape(len(blocks), m, m, m)
-    O = out.reshape(len(blocks), m, m, m)
-    faces = face_neighbours(blocks)
-    for b, (lv, idx, w) in enumerate(blocks):
-        h = w / B
-        u = U[b]
-        c = u[1:-1, 1:-1, 1:-1]
-        nbv = []
-        for ax, sl_lo, sl_hi in ((2, (slice(1, -1), slice(1, -1), slice(0, -2)), (slice(1, -1), slice(1, -1), slice(2, None))),
-                                 (1, (slice(1, -1), slice(0, -2), slice(1, -1)), (slice(1, -1), slice(2, None), slice(1, -1))),
-                                 (0, (slice(0, -2), slice(1, -1), slice(1, -1)), (slice(2, None), slice(1, -1), slice(1, -1)))):
-            # ax is the array axis (0 = z); the face axis in layout terms is 2 - ax
-            for side, sl in ((0, sl_lo), (1, sl_hi)):
-                v = u[sl].copy()
-                if faces[b][(2 - ax, side)][0] == "boundary":
-                    edge = [slice(None)] * 3
-                    edge[ax] = 0 if side == 0 else -1
-                    v[tuple(edge)] = 2.0 * v[tuple(edge)] - c[tuple(edge)]
-                nbv.append(v)
-        # neighbours in the order -x, +x, -y, +y, -z, +z
-        s = c - nbv[0]
-        for v in nbv[1:]:
-            s = s + (c - v)
-        au = s * (1.0 / (h * h))
-        O[b, 1:-1, 1:-1, 1:-1] = c + omega * (h * h / 6.0) * (F[b, 1:-1, 1:-1, 1:-1] - au)
+    U = arr.reshape(nb, m, m, m)
+    F = f.reshape(nb, m, m, m)
+    O = out.reshape(nb, m, m, m)
+    h = block_h(B)
+    c = U[:, 1:-1, 1:-1, 1:-1]
+    O[:, 1:-1, 1:-1, 1:-1] = c + omega * (h * h / 6.0)[:, None, None, None] * (
+        F[:, 1:-1, 1:-1, 1:-1] - apply_operator(arr, B))
     return out
 
 
@@ -383,3 +418,134 @@ def solve_harmonic(B, order):
     hb = np.array([w / B for (_, _, w) in layout()])
     err = np.sqrt(np.sum(hb ** 3 * np.sum(e ** 2, axis=1)))
     return u, err
+
+
+# ---------------------------------------------------------------- multigrid on the layout
+# Sect. 5 solves the composite system with a V(3,3) multigrid: damped Jacobi (omega = 0.8) as
+# smoother and, on the coarsest level, as coarse-grid solver; coarser levels are added until
+# a block holds 4^3 cells.  Every level keeps the 120-block layout with B/2^l cells per block
+# and is rediscretised with its own h; its ghost layers are exchanged by the same rules.  The
+# paper does not state the transfers; the ones used here:
+#   - restriction: the mean of the 8 child residuals (children in z, y, x order);
+#   - prolongation: linear interpolation towards the fine cell from the parent coarse cell and
+#     its three face neighbours on the fine cell's side along x, y and z (weight 1/4 each:
+#     the barycentric weights of the fine centre, a quarter coarse cell from the parent along
+#     every axis, in the tetrahedron of those four centres); exact for linear functions and
+#     reading face ghosts only, which the exchange fills.  A neighbour across the domain
+#     boundary is -e_P (the correction vanishes on the boundary face);
+#   - coarse problems: homogeneous Dirichlet data, initial guess 0.
+
+
+def mg_block_sizes(B, levels=0):
+    """Block sizes of the levels, finest first.  levels = 0: halve while the halved size is
+    even and at least 4 (down to 4^3 cells per block for B = 4 * 2^k)."""
+    if levels < 0:
+        raise ValueError("levels must be >= 0")
+    sizes = [B]
+    if levels == 0:
+        while sizes[-1] % 4 == 0 and sizes[-1] // 2 >= 4:
+            sizes.append(sizes[-1] // 2)
+        return sizes
+    for _ in range(levels - 1):
+        if sizes[-1] % 4 or sizes[-1] // 2 < 4:
+            raise ValueError(f"B={B} does not have {levels} levels of even sizes >= 4")
+        sizes.append(sizes[-1] // 2)
+    return sizes
+
+
+def residual(arr, f, B, order):
+    """Fills the interface ghosts of arr (in place), then returns f - A u at the inner cells,
+    (nb, B, B, B)."""
+    fill(arr, B, order)
+    m = B + 2
+    F = f.reshape(len(layout()), m, m, m)
+    return F[:, 1:-1, 1:-1, 1:-1] - apply_operator(arr, B)
+
+
+def restrict(r):
+    """Coarse right-hand side (nb, B/2, B/2, B/2): the mean of the 8 children of every coarse
+    cell, summed in (z, y, x) order of the children."""
+    s = None
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                c = r[:, dz::2, dy::2, dx::2]
+                s = c if s is None else s + c
+    return 0.125 * s
+
+
+def prolong_add(arr, e, B, order):
+    """arr += P e on the inner cells of every block (level of B cells per block), e the
+    correction of the level below (B/2 cells per block, concatenated arrays).  Fills e's
+    interface ghosts first (in place).  Fine cell (z, y, x) (0-based) has parent (z//2, y//2,
+    x//2) and lies towards d = +1 along an axis where its index is odd, -1 where even; its
+    value is (e_P + e_{P+d_x} + e_{P+d_y} + e_{P+d_z}) / 4."""
+    nb = len(layout())
+    Bc = B // 2
+    mc, m = Bc + 2, B + 2
+    fill(e, Bc, order)
+    E = e.reshape(nb, mc, mc, mc)
+    out = arr.copy()
+    O = out.reshape(nb, m, m, m)
+    bnd = _boundary_faces()
+    P = E[:, 1:-1, 1:-1, 1:-1]
+    inner = slice(1, -1)
+    for pz in (0, 1):
+        for py in (0, 1):
+            for px in (0, 1):
+                nbs = []
+                for ax, p in ((0, px), (1, py), (2, pz)):
+                    arrax = 2 - ax
+                    sl = [inner, inner, inner]
+                    sl[arrax] = slice(2, None) if p else slice(0, -2)
+                    v = E[(slice(None),) + tuple(sl)].copy()
+                    edge = [slice(None)] * 4
+                    edge[1 + arrax] = -1 if p else 0
+                    edge = tuple(edge)
+                    on = bnd[:, ax, p][:, None, None]
+                    v[edge] = np.where(on, -P[edge], v[edge])
+                    nbs.append(v)
+                val = 0.25 * (((P + nbs[0]) + nbs[1]) + nbs[2])
+                O[:, 1 + pz:m - 1:2, 1 + py:m - 1:2, 1 + px:m - 1:2] += val
+    return out
+
+
+def vcycle(arr, f, sizes, order, nu1=3, nu2=3, coarse_iters=256, omega=0.8):
+    """One V(nu1, nu2)-cycle on the level of block size sizes[0] (concatenated arrays; the
+    domain-boundary ghosts of arr hold the Dirichlet data).  Returns the new iterate."""
+    B = sizes[0]
+    if len(sizes) == 1:
+        for _ in range(coarse_iters):
+            arr = jacobi_sweep(arr, f, B, order, omega)
+        return arr
+    for _ in range(nu1):
+        arr = jacobi_sweep(arr, f, B, order, omega)
+    r = residual(arr, f, B, order)
+    nb = len(layout())
+    mc = sizes[1] + 2
+    fc = np.zeros(nb * mc ** 3)
+    fc.reshape(nb, mc, mc, mc)[:, 1:-1, 1:-1, 1:-1] = restrict(r)
+    ec = vcycle(np.zeros_like(fc), fc, sizes[1:], order, nu1, nu2, coarse_iters, omega)
+    arr = prolong_add(arr, ec, B, order)
+    for _ in range(nu2):
+        arr = jacobi_sweep(arr, f, B, order, omega)
+    return arr
+
+
+def residual_norm(arr, f, B, order):
+    """L2 norm of f - A u over all inner cells (unweighted), after a ghost fill."""
+    return float(np.sqrt(np.sum(residual(arr, f, B, order) ** 2)))
+
+
+def mg_solve(arr, f, B, order, tol, max_cycles=35, levels=0, nu1=3, nu2=3, coarse_iters=256,
+             omega=0.8):
+    """V-cycles until the L2 residual norm is <= tol or max_cycles ran (Sect. 5's stopping
+    rule: 1e-16 or 35 cycles).  Returns (u, cycles, residual norm)."""
+    sizes = mg_block_sizes(B, levels)
+    rn = residual_norm(arr, f, B, order)
+    k = 0
+    while rn > tol and k < max_cycles:
+        arr = vcycle(arr, f, sizes, order, nu1, nu2, coarse_iters, omega)
+        k += 1
+        rn = residual_norm(arr, f, B, order)
+    return arr, k, rn

@@ -174,3 +174,124 @@ def test_kappa_pattern_of_table1():
     assert abs(kappa[0] - 1.0) <= 0.05, kappa
     assert 0.3 <= kappa[1] <= 0.55, kappa
     assert abs(kappa[2] - target) <= paper_dev, kappa
+
+
+# ---------------------------------------------------------------- multigrid on the layout
+def test_mg_block_sizes_down_to_four_cells():
+    """Sect. 5: coarser levels until a block holds 4^3 cells."""
+    assert bl.mg_block_sizes(16) == [16, 8, 4]
+    assert bl.mg_block_sizes(256) == [256, 128, 64, 32, 16, 8, 4]
+    assert bl.mg_block_sizes(12) == [12, 6]
+    assert bl.mg_block_sizes(4) == [4]
+    assert bl.mg_block_sizes(16, 2) == [16, 8]
+    with pytest.raises(ValueError):
+        bl.mg_block_sizes(12, 3)
+
+
+def _linear(x, y, z):
+    return 0.7 + 1.3 * x - 2.1 * y + 0.9 * z
+
+
+def _inner_field(B, fn):
+    xc = bl.cell_centres(B)
+    return fn(xc[..., 0], xc[..., 1], xc[..., 2])
+
+
+def test_restriction_is_the_mean_and_exact_on_linear_functions():
+    """The mean of the 8 children of a coarse cell is the value of a linear function at the
+    coarse centre (the centroid of the children); constants stay constants."""
+    Bf = 8
+    r = _inner_field(Bf, _linear)
+    want = _inner_field(Bf // 2, _linear)
+    assert np.abs(bl.restrict(r) - want).max() <= 1e-14 * np.abs(want).max()
+    assert np.array_equal(bl.restrict(np.full((120, 4, 4, 4), 3.0)), np.full((120, 2, 2, 2), 3.0))
+    # every child counts once: a delta in one child gives 1/8 in its parent only
+    d = np.zeros((120, 4, 4, 4))
+    d[5, 3, 0, 1] = 8.0
+    out = bl.restrict(d)
+    assert out[5, 1, 0, 0] == 1.0 and np.count_nonzero(out) == 1
+
+
+def _stored(B, inner):
+    m = B + 2
+    arr = np.zeros((120, m, m, m))
+    arr[:, 1:-1, 1:-1, 1:-1] = inner
+    return arr.reshape(-1)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_prolongation_exact_on_linear_functions(order):
+    """P e reproduces a linear e at every fine cell whose parent and face neighbours are inner
+    or interface-ghost values (interface ghosts of linear data are exact for C2F of order >= 1
+    and for F2C); next to the domain boundary the neighbour is -e_P, exact when e vanishes on
+    that face."""
+    Bf = 8
+    Bc = Bf // 2
+    e = _stored(Bc, _inner_field(Bc, _linear))
+    out = bl.prolong_add(np.zeros(120 * (Bf + 2) ** 3), e, Bf, order)
+    got = out.reshape(120, Bf + 2, Bf + 2, Bf + 2)[:, 1:-1, 1:-1, 1:-1]
+    want = _inner_field(Bf, _linear)
+    xc = bl.cell_centres(Bf)
+    hf = np.array([w / Bf for (_, _, w) in bl.layout()])[:, None, None, None]
+    away = np.all((xc > hf[..., None]) & (xc < 1 - hf[..., None]), axis=-1)
+    assert away.sum() > 0.8 * away.size
+    assert np.abs(got - want)[away].max() <= 1e-13
+    assert np.abs(got - want)[~away].max() > 1e-3  # the boundary rule differs for this e
+    # a linear function vanishing on x = 0: exact next to that face too
+    fn = lambda x, y, z: 3.0 * x  # noqa: E731
+    e = _stored(Bc, _inner_field(Bc, fn))
+    out = bl.prolong_add(np.zeros(120 * (Bf + 2) ** 3), e, Bf, order)
+    got = out.reshape(120, Bf + 2, Bf + 2, Bf + 2)[:, 1:-1, 1:-1, 1:-1]
+    near_x0 = (xc[..., 0] < hf) & np.all((xc[..., 1:] > hf[..., None]) & (xc[..., 1:] < 1 - hf[..., None]), axis=-1)
+    assert near_x0.sum() > 0
+    assert np.abs(got - _inner_field(Bf, fn))[near_x0 | away].max() <= 1e-13
+
+
+_COMPOSITE = {}
+
+
+def composite_solution(B, order):
+    if (B, order) not in _COMPOSITE:
+        A, rhs = bl.composite_system(B, order, bl.harmonic)
+        _COMPOSITE[(B, order)] = bl.solve_system(A, rhs).reshape(120, B, B, B)
+    return _COMPOSITE[(B, order)]
+
+
+def _harmonic_start(B):
+    from paper_2403_08063_amd import inputs
+    u0, _ = inputs.block_harmonic(B)
+    return u0.reshape(-1).copy()
+
+
+def test_vcycle_fixed_point_is_the_composite_solution():
+    """A V(3,3)-cycle leaves the solution of the assembled composite system (GMRES, a library
+    routine independent of the cycle) unchanged: every sweep does, and its zero residual
+    restricts to a zero correction."""
+    B = 8
+    us = composite_solution(B, 2)
+    arr = _harmonic_start(B)
+    arr.reshape(120, B + 2, B + 2, B + 2)[:, 1:-1, 1:-1, 1:-1] = us
+    out = bl.vcycle(arr, np.zeros_like(arr), bl.mg_block_sizes(B), 2)
+    got = out.reshape(120, B + 2, B + 2, B + 2)[:, 1:-1, 1:-1, 1:-1]
+    assert np.abs(got - us).max() <= 1e-11 * np.abs(us).max()
+
+
+def test_vcycle_converges_to_the_composite_solution():
+    """From the boundary data alone, V(3,3)-cycles converge to the composite solution at a
+    per-cycle factor near the uniform solver's (0.19): every cycle after the first reduces
+    the residual norm by at least 0.3 and the distance to the GMRES solution shrinks by the
+    same rate."""
+    B = 8
+    us = composite_solution(B, 2)
+    arr = _harmonic_start(B)
+    f = np.zeros_like(arr)
+    sizes = bl.mg_block_sizes(B)
+    rn = [bl.residual_norm(arr, f, B, 2)]
+    dist = []
+    for _ in range(6):
+        arr = bl.vcycle(arr, f, sizes, 2)
+        rn.append(bl.residual_norm(arr, f, B, 2))
+        dist.append(np.abs(arr.reshape(120, B + 2, B + 2, B + 2)[:, 1:-1, 1:-1, 1:-1] - us).max())
+    factors = np.array(rn[2:]) / np.array(rn[1:-1])
+    assert factors.max() <= 0.3, factors
+    assert dist[-1] <= dist[0] * 0.3 ** 5
