@@ -29,6 +29,21 @@
  * The operator of every block is the 7-point finite-volume one of mg_fv.h with that block's
  * h; damped Jacobi: u <- u + omega (h^2/6) (f - A u).
  *
+ * Multigrid (Sect. 5: V(3,3)-cycles, damped Jacobi with omega = 0.8 as smoother and as
+ * coarsest-level solver, coarser levels until a block holds 4^3 cells): level l keeps the
+ * 120-block layout with B/2^l cells per block and its own h per block, rediscretised and
+ * exchanged by the same rules.  The paper leaves the transfers open; here
+ *  - restriction: the mean of the 8 child residuals of a coarse cell (children in z, y, x
+ *    order), within the block;
+ *  - prolongation: a fine cell lies a quarter coarse cell from its parent P along every axis,
+ *    towards +1 where its 0-based index is odd and -1 where even; its correction is
+ *    (e_P + e_x + e_y + e_z) / 4 with e_a the parent's face neighbour on that side along axis a
+ *    (the barycentric weights of the fine centre in the tetrahedron of those four centres:
+ *    exact for linear functions, and reading only face ghosts, which the exchange fills);
+ *    a neighbour across the domain boundary counts as -e_P (zero correction on the face);
+ *  - coarse problems: zero Dirichlet data and initial guess 0.
+ * Coarse-level arrays live in the workspace; the finest level's are the caller's.
+ *
  * Conventions as in mg.h: device pointers owned by the caller; a caller-provided workspace
  * (mgblk_workspace_bytes, 256-byte aligned), no allocation by the library; all work on the
  * stream given to mgblk_setup; mgblk_residual_norm2 and mgblk_solve synchronise to read norms.
@@ -47,9 +62,15 @@ extern "C" {
 typedef struct mgblk_ctx mgblk_ctx;
 
 typedef struct {
-  int B;         /* cells per block and axis: even, 4 <= B <= 256 */
-  int order;     /* C2F extrapolation order: 0, 1 or 2 (the paper's quadratic scheme) */
-  double omega;  /* Jacobi damping, 0 < omega < 2 */
+  int B;             /* cells per block and axis: even, 4 <= B <= 256 */
+  int order;         /* C2F extrapolation order: 0, 1 or 2 (the paper's quadratic scheme) */
+  double omega;      /* Jacobi damping, 0 < omega < 2 (0.8) */
+  int levels;        /* multigrid levels B, B/2, ...: 0 = halve while the half is even and
+                        >= 4 (down to 4^3 cells per block for B = 4 * 2^k); otherwise every
+                        level but the last must have a size divisible by 4 */
+  int nu1, nu2;      /* pre- and post-smoothing sweeps per level (3, 3) */
+  int coarse_iters;  /* Jacobi iterations on the coarsest level (256) */
+  int max_cycles;    /* mgblk_mg_solve: cycle limit (35) */
 } mgblk_grid;
 
 /* Number of blocks of the layout (120). */
@@ -71,8 +92,27 @@ const char* mgblk_last_error(const mgblk_ctx* ctx);
 mg_status mgblk_fill(mgblk_ctx* ctx, double* u);
 
 /* `sweeps` damped Jacobi sweeps of the composite system, each preceded by a ghost fill; u in
- * place (its domain-boundary ghosts are the Dirichlet data). */
+ * place (its domain-boundary ghosts are the Dirichlet data).  Same as mgblk_smooth(ctx, 0, ...). */
 mg_status mgblk_jacobi(mgblk_ctx* ctx, const double* f, double* u, int sweeps);
+
+/* Number of multigrid levels of the context (level l has B >> l cells per block); 0 for NULL. */
+int mgblk_levels(const mgblk_ctx* ctx);
+
+/* `sweeps` damped Jacobi sweeps on arrays of level `level` (block size B >> level), each
+ * preceded by a ghost fill; u in place, its domain-boundary ghosts being the Dirichlet data. */
+mg_status mgblk_smooth(mgblk_ctx* ctx, int level, const double* f, double* u, int sweeps);
+
+/* Fills u's interface ghosts (level `level`), then fc (level `level`+1) = the mean of the 8
+ * child residuals f - A u of every coarse inner cell.  fc's ghost cells are not written. */
+mg_status mgblk_restrict_residual(mgblk_ctx* ctx, int level, const double* f, double* u,
+                                  double* fc);
+
+/* Fills the interface ghosts of the level-(`level`+1) correction ec (in place; its domain-
+ * boundary ghosts are not read), then u (level `level`) += P ec on the inner cells. */
+mg_status mgblk_prolong_correct(mgblk_ctx* ctx, int level, double* ec, double* u);
+
+/* One V(nu1, nu2)-cycle on the finest level, in place on u. */
+mg_status mgblk_vcycle(mgblk_ctx* ctx, const double* f, double* u);
 
 /* Fills u's ghosts, then *out = sum over all inner cells of (f - A u)^2. */
 mg_status mgblk_residual_norm2(mgblk_ctx* ctx, const double* f, double* u, double* out);
@@ -82,6 +122,13 @@ mg_status mgblk_residual_norm2(mgblk_ctx* ctx, const double* f, double* u, doubl
  * MG_ENOCONV if the tolerance was not reached. */
 mg_status mgblk_solve(mgblk_ctx* ctx, const double* f, double* u, double tol, int max_sweeps,
                       int check_every, int* sweeps, double* resnorm);
+
+/* V-cycles until the L2 residual norm (over all inner cells, unweighted) is <= tol or
+ * max_cycles cycles ran (Sect. 5: 1e-16 or 35); synchronises once per cycle to read the norm.
+ * *cycles and *resnorm (optional) receive the count and the last norm.  MG_ENOCONV if the
+ * tolerance was not reached (u holds the last iterate). */
+mg_status mgblk_mg_solve(mgblk_ctx* ctx, const double* f, double* u, double tol, int* cycles,
+                         double* resnorm);
 
 #ifdef __cplusplus
 }

@@ -33,6 +33,8 @@ EXPORTS = [
     # include/mg_blocks.h
     "mgblk_block_count", "mgblk_workspace_bytes", "mgblk_setup", "mgblk_destroy",
     "mgblk_last_error", "mgblk_fill", "mgblk_jacobi", "mgblk_residual_norm2", "mgblk_solve",
+    "mgblk_levels", "mgblk_smooth", "mgblk_restrict_residual", "mgblk_prolong_correct",
+    "mgblk_vcycle", "mgblk_mg_solve",
 ]
 
 
@@ -49,7 +51,9 @@ class MgFvGrid(ctypes.Structure):
 
 
 class MgBlkGrid(ctypes.Structure):
-    _fields_ = [("B", ctypes.c_int), ("order", ctypes.c_int), ("omega", ctypes.c_double)]
+    _fields_ = [("B", ctypes.c_int), ("order", ctypes.c_int), ("omega", ctypes.c_double),
+                ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("coarse_iters", ctypes.c_int), ("max_cycles", ctypes.c_int)]
 
 
 class MgError(RuntimeError):
@@ -117,6 +121,12 @@ def lib() -> ctypes.CDLL:
         "mgblk_jacobi": (i, [P, P, P, i]),
         "mgblk_residual_norm2": (i, [P, P, P, PD]),
         "mgblk_solve": (i, [P, P, P, d, i, i, PI, PD]),
+        "mgblk_levels": (i, [P]),
+        "mgblk_smooth": (i, [P, i, P, P, i]),
+        "mgblk_restrict_residual": (i, [P, i, P, P, P]),
+        "mgblk_prolong_correct": (i, [P, i, P, P]),
+        "mgblk_vcycle": (i, [P, P, P]),
+        "mgblk_mg_solve": (i, [P, P, P, d, PI, PD]),
     }
     for name in EXPORTS:
         res, args = sig[name]

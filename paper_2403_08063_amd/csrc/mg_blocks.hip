@@ -1,14 +1,17 @@
 // The 2:1 refined block layout of Sect. 5 and its ghost-layer exchange (Sect. 3: same-level
 // copies, F2C linear interpolation, C2F extrapolation of order 0, 1 or 2 with the remapping
 // at block edges), behind the C ABI of include/mg_blocks.h, with a damped-Jacobi solver of
-// the composite cell-centred system.
+// the composite cell-centred system: plain sweeps, or V-cycles over levels of the same layout
+// with B/2^l cells per block (Sect. 5's solver: damped Jacobi as smoother and coarsest solver).
 //
 // The host builds the layout's face table once (per block and face: the kind of neighbour,
 // the neighbouring block or blocks and, for C2F, the quadrant of the coarse face); the fill
 // kernel runs one thread per ghost cell of every block face and evaluates its rule on the
 // fly: the C2F value is the tensor product of three 1D Lagrange weight sets (normal,
 // first and second tangential axis), the bases chosen per cell as the rule prescribes.  The
-// Jacobi kernel runs one thread per inner cell of all blocks, each block with its own h.
+// Jacobi kernel runs one thread per inner cell of all blocks, each block with its own h; the
+// restriction one thread per coarse cell (its 8 children's residuals, mean), the
+// prolongation one thread per fine cell (parent and three face neighbours, weight 1/4 each).
 #include "../../include/mg_blocks.h"
 #include "mg_kernels.h"
 
@@ -147,15 +150,24 @@ C2FWeights c2f_weights(int order)
 
 }  // namespace
 
+// one level of the hierarchy: B cells per block; u, f only below the finest level (the
+// caller owns the finest level's arrays), t the second buffer of the Jacobi sweeps
+struct BlkLevel {
+  int B = 0;
+  size_t cnt = 0;         // doubles of all blocks
+  double* hs = nullptr;   // device: h of every block
+  double* u = nullptr;
+  double* t = nullptr;
+  double* f = nullptr;
+};
+
 struct mgblk_ctx {
   mgblk_grid g{};
   hipStream_t s = nullptr;
   int* faces = nullptr;   // device face table
-  double* hs = nullptr;   // device: h of every block
-  double* t = nullptr;    // second buffer of the blocks
   double* partial = nullptr;
   double* scal = nullptr;
-  size_t cnt = 0;         // doubles of all blocks
+  std::vector<BlkLevel> lv;
   std::vector<double> hhost;
   C2FWeights w{};
   char err[512] = "no error";
@@ -180,7 +192,26 @@ mg_status blk_validate(const mgblk_grid* g)
     return blk_fail(nullptr, MG_EINVAL, "B must be even in [4, 256] (got %d)", g->B);
   if (g->order < 0 || g->order > 2) return blk_fail(nullptr, MG_EINVAL, "order must be 0, 1 or 2");
   if (!(g->omega > 0.0 && g->omega < 2.0)) return blk_fail(nullptr, MG_EINVAL, "omega must be in (0, 2)");
+  if (g->levels < 0 || g->levels > 8) return blk_fail(nullptr, MG_EINVAL, "levels must be in [0, 8]");
+  for (int l = 1, b = g->B; l < g->levels; ++l, b /= 2)
+    if (b % 4 || b / 2 < 4)
+      return blk_fail(nullptr, MG_EINVAL, "B=%d has no %d levels of even block sizes >= 4", g->B, g->levels);
+  if (g->nu1 < 0 || g->nu2 < 0 || g->coarse_iters < 0)
+    return blk_fail(nullptr, MG_EINVAL, "nu1, nu2 and coarse_iters must be >= 0");
+  if (g->max_cycles < 1) return blk_fail(nullptr, MG_EINVAL, "max_cycles must be >= 1");
   return MG_OK;
+}
+
+// block sizes of the levels: `levels` of them, or (0) halving while the half is even and >= 4
+std::vector<int> level_sizes(const mgblk_grid* g)
+{
+  std::vector<int> out{g->B};
+  if (g->levels == 0) {
+    while (out.back() % 4 == 0 && out.back() / 2 >= 4) out.push_back(out.back() / 2);
+  } else {
+    while ((int)out.size() < g->levels) out.push_back(out.back() / 2);
+  }
+  return out;
 }
 
 struct BlkCarver {
@@ -198,20 +229,28 @@ struct BlkCarver {
 
 void blk_layout(const mgblk_grid* g, BlkCarver& cv, mgblk_ctx* c)
 {
-  const size_t m = (size_t)g->B + 2;
-  const size_t cnt = (size_t)kBlocks * m * m * m;
   int* faces = cv.take<int>((size_t)kBlocks * 6 * kFaceInts);
-  double* hs = cv.take<double>(kBlocks);
-  double* t = cv.take<double>(cnt);
   double* partial = cv.take<double>(kBlkNormBlocks);
   double* scal = cv.take<double>(8);
+  std::vector<BlkLevel> lv;
+  for (int B : level_sizes(g)) {
+    BlkLevel L;
+    const size_t m = (size_t)B + 2;
+    L.B = B;
+    L.cnt = (size_t)kBlocks * m * m * m;
+    L.hs = cv.take<double>(kBlocks);
+    L.t = cv.take<double>(L.cnt);
+    if (!lv.empty()) {
+      L.u = cv.take<double>(L.cnt);
+      L.f = cv.take<double>(L.cnt);
+    }
+    lv.push_back(L);
+  }
   if (c) {
     c->faces = faces;
-    c->hs = hs;
-    c->t = t;
     c->partial = partial;
     c->scal = scal;
-    c->cnt = cnt;
+    c->lv = lv;
   }
 }
 
@@ -390,22 +429,106 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) out[0] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
-void fill(mgblk_ctx* c, double* u)
+// ---------------------------------------------------------------- multigrid transfers
+constexpr int kXferThreads = 64;
+
+// fc = mean of the 8 children's residuals f - A u (children in z, y, x order) for every coarse
+// inner cell; uc (optional) = 0 there.  B: fine block size, u's ghosts filled.
+__global__ void __launch_bounds__(kXferThreads)
+    k_blk_restrict(int B, const int* __restrict__ faces, const double* __restrict__ hs,
+                   const double* __restrict__ f, const double* __restrict__ u,
+                   double* __restrict__ fc, double* __restrict__ uc)
 {
-  const int B = c->g.B;
-  const dim3 grid((unsigned)((B * B + kFillThreads - 1) / kFillThreads), 6, kBlocks);
-  k_blk_fill<<<grid, kFillThreads, 0, c->s>>>(B, c->g.order, c->w, c->faces, u);
+  const int Bc = B / 2;
+  const int X = blockIdx.x * kXferThreads + threadIdx.x, Y = blockIdx.y;
+  const int b = blockIdx.z / Bc, Z = blockIdx.z % Bc;
+  if (X >= Bc) return;
+  const int m = B + 2;
+  const double h = hs[b];
+  const double ih2 = 1.0 / (h * h);
+  const int* fb = faces + (size_t)b * 6 * kFaceInts;
+  double s = 0.0;
+  bool first = true;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int z = 1 + 2 * Z + dz, y = 1 + 2 * Y + dy, x = 1 + 2 * X + dx;
+        const size_t i = bidx(m, b, z, y, x);
+        const double r = f[i] - blk_apply_at(B, fb, ih2, u, i, z, y, x);
+        s = first ? r : s + r;
+        first = false;
+      }
+  const size_t ci = bidx(Bc + 2, b, Z + 1, Y + 1, X + 1);
+  fc[ci] = 0.125 * s;
+  if (uc) uc[ci] = 0.0;
 }
 
-// sweeps with a fill before each, alternating u and the second buffer; returns the result
-double* sweeps(mgblk_ctx* c, const double* f, double* u, int count)
+// u += P e on the inner cells (B: fine block size; e: B/2 cells per block, interface ghosts
+// filled).  A fine cell lies towards +1 along an axis where its 0-based index is odd, -1
+// where even; its correction is (e_P + e_x + e_y + e_z) / 4 with e_a the parent's neighbour on
+// that side along axis a, -e_P where that neighbour lies across the domain boundary.
+__global__ void __launch_bounds__(kXferThreads)
+    k_blk_prolong(int B, const int* __restrict__ faces, const double* __restrict__ e,
+                  double* __restrict__ u)
 {
-  const int B = c->g.B;
+  const int x0 = blockIdx.x * kXferThreads + threadIdx.x, y0 = blockIdx.y;
+  const int b = blockIdx.z / B, z0 = blockIdx.z % B;  // 0-based fine inner indices
+  if (x0 >= B) return;
+  const int Bc = B / 2, mc = Bc + 2;
+  const int* fb = faces + (size_t)b * 6 * kFaceInts;
+  const int X = 1 + x0 / 2, Y = 1 + y0 / 2, Z = 1 + z0 / 2;
+  const int dx = (x0 & 1) ? 1 : -1, dy = (y0 & 1) ? 1 : -1, dz = (z0 & 1) ? 1 : -1;
+  const double eP = e[bidx(mc, b, Z, Y, X)];
+  auto across = [&](int n, int face) {  // neighbour index n along an axis in the ghost layer?
+    return (n == 0 || n == Bc + 1) && fb[face * kFaceInts] == kFaceBoundary;
+  };
+  const double ex = across(X + dx, (x0 & 1)) ? -eP : e[bidx(mc, b, Z, Y, X + dx)];
+  const double ey = across(Y + dy, 2 + (y0 & 1)) ? -eP : e[bidx(mc, b, Z, Y + dy, X)];
+  const double ez = across(Z + dz, 4 + (z0 & 1)) ? -eP : e[bidx(mc, b, Z + dz, Y, X)];
+  const size_t i = bidx(B + 2, b, z0 + 1, y0 + 1, x0 + 1);
+  u[i] = u[i] + 0.25 * (((eP + ex) + ey) + ez);
+}
+
+// dst = src on the domain-boundary ghost cells (the Dirichlet data of the second buffer)
+__global__ void __launch_bounds__(kFillThreads)
+    k_blk_copy_boundary(int B, const int* __restrict__ faces, const double* __restrict__ src,
+                        double* __restrict__ dst)
+{
+  const int q = blockIdx.x * kFillThreads + threadIdx.x;
+  if (q >= B * B) return;
+  const int f = blockIdx.y, b = blockIdx.z;
+  if (faces[((size_t)b * 6 + f) * kFaceInts] != kFaceBoundary) return;
+  int x, y, z;
+  face_coords(f >> 1, (f & 1) ? B + 1 : 0, 1 + q % B, 1 + q / B, x, y, z);
+  const size_t i = bidx(B + 2, b, z, y, x);
+  dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- host drivers
+dim3 face_grid(int B) { return dim3((unsigned)((B * B + kFillThreads - 1) / kFillThreads), 6, kBlocks); }
+
+void fill(mgblk_ctx* c, int l, double* u)
+{
+  const int B = c->lv[l].B;
+  k_blk_fill<<<face_grid(B), kFillThreads, 0, c->s>>>(B, c->g.order, c->w, c->faces, u);
+}
+
+void copy_boundary(mgblk_ctx* c, int l, const double* src, double* dst)
+{
+  const int B = c->lv[l].B;
+  k_blk_copy_boundary<<<face_grid(B), kFillThreads, 0, c->s>>>(B, c->faces, src, dst);
+}
+
+// `count` sweeps on level l with a fill before each, alternating between cur and oth (which
+// holds the same domain-boundary ghosts); returns the buffer holding the result
+double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, int count)
+{
+  const BlkLevel& L = c->lv[l];
+  const int B = L.B;
   const dim3 grid((unsigned)((B + kJacThreads - 1) / kJacThreads), B, kBlocks * B);
-  double *cur = u, *oth = c->t;
   for (int s = 0; s < count; ++s) {
-    fill(c, cur);
-    k_blk_jacobi<<<grid, kJacThreads, 0, c->s>>>(B, c->g.omega, c->faces, c->hs, f, cur, oth);
+    fill(c, l, cur);
+    k_blk_jacobi<<<grid, kJacThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth);
     double* x = cur;
     cur = oth;
     oth = x;
@@ -413,16 +536,59 @@ double* sweeps(mgblk_ctx* c, const double* f, double* u, int count)
   return cur;
 }
 
+// fills u's ghosts on level l, fc (level l+1) = restricted residual, uc inner = 0 if given
+void restrict_residual(mgblk_ctx* c, int l, const double* f, double* u, double* fc, double* uc)
+{
+  const BlkLevel& L = c->lv[l];
+  const int Bc = L.B / 2;
+  fill(c, l, u);
+  const dim3 grid((unsigned)((Bc + kXferThreads - 1) / kXferThreads), Bc, kBlocks * Bc);
+  k_blk_restrict<<<grid, kXferThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc);
+}
+
+// fills ec's interface ghosts (level l+1), then u (level l) += P ec
+void prolong_correct(mgblk_ctx* c, int l, double* ec, double* u)
+{
+  const int B = c->lv[l].B;
+  fill(c, l + 1, ec);
+  const dim3 grid((unsigned)((B + kXferThreads - 1) / kXferThreads), B, kBlocks * B);
+  k_blk_prolong<<<grid, kXferThreads, 0, c->s>>>(B, c->faces, ec, u);
+}
+
+// V(nu1, nu2) on level l from the iterate in x (y: the level's second buffer); returns the
+// buffer holding the result.  Coarse problems start from 0 in the level's u.
+double* vcycle_rec(mgblk_ctx* c, int l, const double* f, double* x, double* y)
+{
+  const int last = (int)c->lv.size() - 1;
+  if (l == last) return sweeps(c, l, f, x, y, c->g.coarse_iters);
+  double* cur = sweeps(c, l, f, x, y, c->g.nu1);
+  double* oth = cur == x ? y : x;
+  BlkLevel& C = c->lv[l + 1];
+  restrict_residual(c, l, f, cur, C.f, C.u);
+  double* ec = vcycle_rec(c, l + 1, C.f, C.u, C.t);
+  prolong_correct(c, l, ec, cur);
+  return sweeps(c, l, f, cur, oth, c->g.nu2);
+}
+
 mg_status norm2(mgblk_ctx* c, const double* f, double* u, double* out)
 {
-  fill(c, u);
-  k_blk_norm2<<<kBlkNormBlocks, 256, 0, c->s>>>(c->g.B, c->faces, c->hs, f, u, c->partial);
+  fill(c, 0, u);
+  k_blk_norm2<<<kBlkNormBlocks, 256, 0, c->s>>>(c->lv[0].B, c->faces, c->lv[0].hs, f, u, c->partial);
   k_blk_sum<<<1, 256, 0, c->s>>>(c->partial, kBlkNormBlocks, c->scal);
   if (mg_status st = blk_hip(c, hipGetLastError(), "norm")) return st;
   if (mg_status st = blk_hip(c, hipMemcpyAsync(out, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->s),
                              "reading the norm"))
     return st;
   return blk_hip(c, hipStreamSynchronize(c->s), "stream synchronisation");
+}
+
+// one V-cycle on the finest level, the result in u
+void vcycle_top(mgblk_ctx* c, const double* f, double* u)
+{
+  BlkLevel& F = c->lv[0];
+  copy_boundary(c, 0, u, F.t);
+  double* r = vcycle_rec(c, 0, f, u, F.t);
+  if (r != u) mgk::copy<double>(c->s, F.cnt, r, u);
 }
 
 }  // namespace
@@ -464,13 +630,20 @@ mg_status mgblk_setup(const mgblk_grid* grid, void* workspace, size_t bytes, voi
     return blk_fail(nullptr, MG_EINVAL, "layout has %zu blocks", blocks.size());
   }
   const std::vector<int> faces = build_faces(blocks);
-  c->hhost.resize(kBlocks);
-  for (int b = 0; b < kBlocks; ++b) c->hhost[b] = blocks[b].width / grid->B;
+  const int nlev = (int)c->lv.size();
+  c->hhost.resize((size_t)kBlocks * nlev);
+  for (int l = 0; l < nlev; ++l)
+    for (int b = 0; b < kBlocks; ++b) c->hhost[(size_t)l * kBlocks + b] = blocks[b].width / c->lv[l].B;
   mg_status st = blk_hip(c, hipMemcpyAsync(c->faces, faces.data(), faces.size() * sizeof(int),
                                            hipMemcpyHostToDevice, c->s), "uploading the face table");
-  if (!st)
-    st = blk_hip(c, hipMemcpyAsync(c->hs, c->hhost.data(), kBlocks * sizeof(double),
+  for (int l = 0; l < nlev && !st; ++l)
+    st = blk_hip(c, hipMemcpyAsync(c->lv[l].hs, &c->hhost[(size_t)l * kBlocks], kBlocks * sizeof(double),
                                    hipMemcpyHostToDevice, c->s), "uploading the block widths");
+  // coarse levels: zero Dirichlet data in the ghost layers of both buffers, never rewritten
+  for (int l = 1; l < nlev && !st; ++l) {
+    st = blk_hip(c, hipMemsetAsync(c->lv[l].u, 0, c->lv[l].cnt * sizeof(double), c->s), "clearing a level");
+    if (!st) st = blk_hip(c, hipMemsetAsync(c->lv[l].t, 0, c->lv[l].cnt * sizeof(double), c->s), "clearing a level");
+  }
   // the host tables are pageable: finish the copies before they go out of scope
   if (!st) st = blk_hip(c, hipStreamSynchronize(c->s), "setup");
   if (st) {
@@ -490,18 +663,56 @@ mg_status mgblk_fill(mgblk_ctx* c, double* u)
 {
   if (!c) return blk_fail(nullptr, MG_EINVAL, "context is NULL");
   if (!u) return blk_fail(c, MG_EINVAL, "u is NULL");
-  fill(c, u);
+  fill(c, 0, u);
   return blk_hip(c, hipGetLastError(), "ghost fill");
 }
 
 mg_status mgblk_jacobi(mgblk_ctx* c, const double* f, double* u, int count)
 {
+  return mgblk_smooth(c, 0, f, u, count);
+}
+
+int mgblk_levels(const mgblk_ctx* c) { return c ? (int)c->lv.size() : 0; }
+
+mg_status mgblk_smooth(mgblk_ctx* c, int level, const double* f, double* u, int count)
+{
   if (!c) return blk_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (level < 0 || level >= (int)c->lv.size()) return blk_fail(c, MG_EINVAL, "level %d out of range", level);
   if (!f || !u || count < 0) return blk_fail(c, MG_EINVAL, "bad Jacobi arguments");
-  mgk::copy<double>(c->s, c->cnt, u, c->t);  // the second buffer's boundary ghosts
-  double* r = sweeps(c, f, u, count);
-  if (r != u) mgk::copy<double>(c->s, c->cnt, r, u);
+  BlkLevel& L = c->lv[level];
+  if (u == L.t) return blk_fail(c, MG_EINVAL, "u is the level's internal buffer");
+  copy_boundary(c, level, u, L.t);
+  double* r = sweeps(c, level, f, u, L.t, count);
+  if (r != u) mgk::copy<double>(c->s, L.cnt, r, u);
   return blk_hip(c, hipGetLastError(), "Jacobi");
+}
+
+mg_status mgblk_restrict_residual(mgblk_ctx* c, int level, const double* f, double* u, double* fc)
+{
+  if (!c) return blk_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (level < 0 || level + 1 >= (int)c->lv.size())
+    return blk_fail(c, MG_EINVAL, "level %d has no coarser level", level);
+  if (!f || !u || !fc) return blk_fail(c, MG_EINVAL, "f, u and fc must be non-NULL");
+  restrict_residual(c, level, f, u, fc, nullptr);
+  return blk_hip(c, hipGetLastError(), "restriction");
+}
+
+mg_status mgblk_prolong_correct(mgblk_ctx* c, int level, double* ec, double* u)
+{
+  if (!c) return blk_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (level < 0 || level + 1 >= (int)c->lv.size())
+    return blk_fail(c, MG_EINVAL, "level %d has no coarser level", level);
+  if (!ec || !u) return blk_fail(c, MG_EINVAL, "ec and u must be non-NULL");
+  prolong_correct(c, level, ec, u);
+  return blk_hip(c, hipGetLastError(), "prolongation");
+}
+
+mg_status mgblk_vcycle(mgblk_ctx* c, const double* f, double* u)
+{
+  if (!c) return blk_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (!f || !u) return blk_fail(c, MG_EINVAL, "f and u must be non-NULL");
+  vcycle_top(c, f, u);
+  return blk_hip(c, hipGetLastError(), "V-cycle");
 }
 
 mg_status mgblk_residual_norm2(mgblk_ctx* c, const double* f, double* u, double* out)
@@ -518,15 +729,16 @@ mg_status mgblk_solve(mgblk_ctx* c, const double* f, double* u, double tol, int 
   if (!f || !u) return blk_fail(c, MG_EINVAL, "f and u must be non-NULL");
   if (!(tol >= 0) || max_sweeps < 0 || check_every < 2 || (check_every & 1))
     return blk_fail(c, MG_EINVAL, "tol >= 0, max_sweeps >= 0, check_every even and >= 2");
-  mgk::copy<double>(c->s, c->cnt, u, c->t);
+  BlkLevel& F = c->lv[0];
+  copy_boundary(c, 0, u, F.t);
   double rn2 = 0;
   mg_status st = norm2(c, f, u, &rn2);
   double rn = std::sqrt(rn2);
   int k = 0;
   while (!st && std::isfinite(rn) && rn > tol && k < max_sweeps) {
     const int n = check_every < max_sweeps - k ? check_every : max_sweeps - k;
-    double* r = sweeps(c, f, u, n);
-    if (r != u) mgk::copy<double>(c->s, c->cnt, r, u);
+    double* r = sweeps(c, 0, f, u, F.t, n);
+    if (r != u) mgk::copy<double>(c->s, F.cnt, r, u);
     k += n;
     st = norm2(c, f, u, &rn2);
     rn = std::sqrt(rn2);
@@ -536,6 +748,30 @@ mg_status mgblk_solve(mgblk_ctx* c, const double* f, double* u, double tol, int 
   if (st) return st;
   if (!std::isfinite(rn)) return blk_fail(c, MG_ENAN, "residual norm is not finite after %d sweeps", k);
   if (rn > tol) return blk_fail(c, MG_ENOCONV, "residual norm %.3e > tol %.3e after %d sweeps", rn, tol, k);
+  return MG_OK;
+}
+
+mg_status mgblk_mg_solve(mgblk_ctx* c, const double* f, double* u, double tol, int* cycles,
+                         double* resnorm)
+{
+  if (!c) return blk_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (!f || !u) return blk_fail(c, MG_EINVAL, "f and u must be non-NULL");
+  if (!(tol >= 0)) return blk_fail(c, MG_EINVAL, "tol must be >= 0");
+  double rn2 = 0;
+  mg_status st = norm2(c, f, u, &rn2);
+  double rn = std::sqrt(rn2);
+  int k = 0;
+  while (!st && std::isfinite(rn) && rn > tol && k < c->g.max_cycles) {
+    vcycle_top(c, f, u);
+    ++k;
+    st = norm2(c, f, u, &rn2);
+    rn = std::sqrt(rn2);
+  }
+  if (cycles) *cycles = k;
+  if (resnorm) *resnorm = rn;
+  if (st) return st;
+  if (!std::isfinite(rn)) return blk_fail(c, MG_ENAN, "residual norm is not finite after %d cycles", k);
+  if (rn > tol) return blk_fail(c, MG_ENOCONV, "residual norm %.3e > tol %.3e after %d cycles", rn, tol, k);
   return MG_OK;
 }
 

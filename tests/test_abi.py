@@ -8,7 +8,7 @@ import re
 import pytest
 
 from paper_2403_08063_amd import _lib
-from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgFvGrid, MgGrid
+from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgBlkGrid, MgFvGrid, MgGrid
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -130,3 +130,37 @@ def test_fv_workspace_size():
         want += per * (1 if l == 0 else 3)
     got = fv_bytes(N=N, levels=levels)
     assert want <= got <= want + 16384 * 8 + 2048
+
+
+# ---------------------------------------------------------------- refined block layout
+def blk_bytes(**kw):
+    g = dict(B=16, order=2, omega=0.8, levels=0, nu1=3, nu2=3, coarse_iters=256, max_cycles=35)
+    g.update(kw)
+    return _lib.lib().mgblk_workspace_bytes(ctypes.byref(MgBlkGrid(**g)))
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(B=4), dict(B=12), dict(B=256), dict(B=16, levels=3),
+                                dict(B=12, levels=2), dict(order=0), dict(coarse_iters=0)])
+def test_blk_valid_grids(kw):
+    assert blk_bytes(**kw) > 0
+
+
+@pytest.mark.parametrize("kw", [dict(B=2), dict(B=7), dict(B=258), dict(order=3), dict(omega=2.0),
+                                dict(B=16, levels=4), dict(B=12, levels=3), dict(levels=-1),
+                                dict(nu1=-1), dict(coarse_iters=-1), dict(max_cycles=0)])
+def test_blk_invalid_grids_need_no_workspace(kw):
+    assert blk_bytes(**kw) == 0
+
+
+def test_blk_workspace_size():
+    """Automatic levels down to 4^3 cells per block: a second buffer on every level plus
+    correction and right-hand side below the finest, 120 (B_l + 2)^3 doubles each (256-byte
+    aligned), plus the face table, block widths and partial sums."""
+    B = 16
+    want = 0
+    for l, Bl in enumerate((16, 8, 4)):
+        per = -(-(120 * (Bl + 2) ** 3 * 8) // 256) * 256
+        want += per * (1 if l == 0 else 3)
+    got = blk_bytes(B=B)
+    assert want <= got <= want + 120 * 6 * 8 * 4 + 3 * 120 * 8 + 1024 * 8 + 8 * 256
+    assert blk_bytes(B=B, levels=1) < got

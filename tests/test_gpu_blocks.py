@@ -1,11 +1,13 @@
 """GPU parity of the refined block layout (include/mg_blocks.h) against the oracle
 (oracle/blocks.py): the ghost exchange of Sect. 3 (same-level copies, F2C, C2F of order 0, 1
-and 2 with the remapping cases), the per-block Jacobi sweep of the composite system, and the
-composite solve of Eq. 1-2 with Table 1's kappa pattern.
+and 2 with the remapping cases), the per-block Jacobi sweep of the composite system, the
+multigrid transfers and V(3,3)-cycles of Sect. 5's solver, and the composite solve of Eq. 1-2
+with Table 1's kappa pattern.
 
 Tolerances: a ghost value is a weighted sum of up to 27 inner values whose weights the GPU
 computes with the oracle's operations, summed in a different order: <= 1e-13 of the data's
-magnitude.  Sweeps inherit that.  Solves: the GPU's Jacobi iteration to a residual reduction of
+magnitude.  Sweeps, transfers and V-cycles inherit that (the cycle is contractive): <= 1e-11 of the
+data's magnitude.  Solves: the GPU's Jacobi iteration or V-cycles to a residual reduction of
 1e-11 against the oracle's GMRES solution: <= 1e-8 relative.
 """
 import numpy as np
@@ -70,6 +72,17 @@ def test_jacobi_sweeps_match_oracle(order):
     rb.close()
 
 
+_COMPOSITE = {}
+
+
+def composite(B, order):
+    """The oracle's composite solution (GMRES on the assembled system), cached."""
+    if (B, order) not in _COMPOSITE:
+        A, rhs = bl.composite_system(B, order, bl.harmonic)
+        _COMPOSITE[(B, order)] = bl.solve_system(A, rhs).reshape(120, B, B, B)
+    return _COMPOSITE[(B, order)]
+
+
 def gpu_solve(B, order):
     u0, exact = inputs.block_harmonic(B)
     rb = RefinedBlocks(B, order, device=DEV)
@@ -92,8 +105,7 @@ def test_composite_solve_matches_oracle(order):
     u, err, info = gpu_solve(B, order)
     say(f"  sweeps={info.cycles} residual={info.relres:.3e} L2 error={err:.4e}")
     assert info.converged
-    A, rhs = bl.composite_system(B, order, bl.harmonic)
-    uo = bl.solve_system(A, rhs).reshape(120, B, B, B)
+    uo = composite(B, order)
     inner = u[:, 1:-1, 1:-1, 1:-1]
     assert np.abs(inner - uo).max() <= 1e-8 * np.abs(uo).max()
 
@@ -115,3 +127,148 @@ def test_kappa_pattern_on_gpu():
     say(f"  kappa constant {k0:.4f}; quadratic {k2a:.4f}, {k2b:.4f}")
     assert abs(k0 - 1.0) <= 0.05
     assert abs(k2a - 0.2563) <= 2e-3 and abs(k2b - 0.2519) <= 2e-3
+
+
+# ---------------------------------------------------------------- multigrid (Sect. 5's solver)
+def _random_level(rng, B, lo=-1.0, hi=1.0):
+    return rng.uniform(lo, hi, (120, B + 2, B + 2, B + 2))
+
+
+@pytest.mark.parametrize("B,order", [(8, 2), (16, 0), (16, 1), (16, 2)])
+def test_transfers_match_oracle(B, order):
+    say(f"blocks transfers B={B} order={order}")
+    rng = np.random.default_rng(300 + B + order)
+    rb = RefinedBlocks(B, order, device=DEV)
+    assert rb.levels == len(bl.mg_block_sizes(B))
+    u, f = _random_level(rng, B), _random_level(rng, B, -5.0, 5.0)
+    ug = torch.from_numpy(u.copy()).to(DEV)
+    fc = rb.zeros(1)
+    rb.restrict_residual(0, torch.from_numpy(f).to(DEV), ug, fc)
+    uo = u.copy().reshape(-1)
+    want = bl.restrict(bl.residual(uo, f.reshape(-1), B, order))
+    got = host(fc)[:, 1:-1, 1:-1, 1:-1]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    assert np.abs(host(ug).reshape(-1) - uo).max() <= 1e-13  # u's ghosts filled as the oracle's
+    # prolongation of a random correction (its ghosts hold junk the fill must overwrite)
+    Bc = B // 2
+    e, u2 = _random_level(rng, Bc), _random_level(rng, B)
+    eg, u2g = torch.from_numpy(e.copy()).to(DEV), torch.from_numpy(u2.copy()).to(DEV)
+    rb.prolong_correct(0, eg, u2g)
+    want = bl.prolong_add(u2.copy().reshape(-1), e.copy().reshape(-1), B, order).reshape(u2.shape)
+    got = host(u2g)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    rb.close()
+
+
+def test_coarse_level_smoothing_matches_oracle():
+    B, order = 16, 2
+    say("blocks coarse-level sweeps")
+    rng = np.random.default_rng(11)
+    rb = RefinedBlocks(B, order, device=DEV)
+    Bc = rb.level_B(1)
+    u = np.zeros((120, Bc + 2, Bc + 2, Bc + 2))
+    u[:, 1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, (120, Bc, Bc, Bc))
+    f = _random_level(rng, Bc, -5.0, 5.0)
+    ug = torch.from_numpy(u.copy()).to(DEV)
+    rb.smooth(1, torch.from_numpy(f).to(DEV), ug, 3)
+    uo = u.copy().reshape(-1)
+    for _ in range(3):
+        uo = bl.jacobi_sweep(uo, f.reshape(-1), Bc, order)
+    got = host(ug)[:, 1:-1, 1:-1, 1:-1]
+    want = uo.reshape(u.shape)[:, 1:-1, 1:-1, 1:-1]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    rb.close()
+
+
+def _start(B, rng):
+    """Harmonic Dirichlet data, U[-1,1] inner cells, U[-5,5] right-hand side."""
+    u0, _ = inputs.block_harmonic(B)
+    u0[:, 1:-1, 1:-1, 1:-1] = rng.uniform(-1.0, 1.0, (120, B, B, B))
+    f = _random_level(rng, B, -5.0, 5.0)
+    return u0, f
+
+
+@pytest.mark.parametrize("B,order,kw,cycles", [
+    (8, 0, {}, 2), (8, 1, {}, 2), (8, 2, {}, 2), (16, 2, {}, 2),
+    (16, 2, dict(nu1=1, nu2=2, coarse_iters=5), 1),   # odd sweep counts: buffer swaps
+    (8, 2, dict(levels=1, coarse_iters=3), 1),        # a single level: the sweeps alone
+    (12, 2, {}, 1),                                   # 12 -> 6 cells per block
+])
+def test_vcycle_matches_oracle(B, order, kw, cycles):
+    say(f"blocks V-cycle B={B} order={order} {kw} x{cycles}")
+    rng = np.random.default_rng(500 + B + 10 * order)
+    u0, f = _start(B, rng)
+    rb = RefinedBlocks(B, order, device=DEV, **kw)
+    ug = torch.from_numpy(u0.copy()).to(DEV)
+    fg = torch.from_numpy(f).to(DEV)
+    sizes = bl.mg_block_sizes(B, kw.get("levels", 0))
+    assert rb.levels == len(sizes)
+    opts = dict(nu1=kw.get("nu1", 3), nu2=kw.get("nu2", 3), coarse_iters=kw.get("coarse_iters", 256))
+    uo = u0.copy().reshape(-1)
+    for _ in range(cycles):
+        rb.vcycle(fg, ug)
+        uo = bl.vcycle(uo, f.reshape(-1), sizes, order, **opts)
+    got = host(ug)[:, 1:-1, 1:-1, 1:-1]
+    want = uo.reshape(u0.shape)[:, 1:-1, 1:-1, 1:-1]
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+    # the Dirichlet data is untouched
+    bmask = np.zeros(u0.shape, dtype=bool)
+    for b, i, _ in bl.ghost_map(B, order)[4]:
+        bmask.reshape(120, -1)[b, i] = True
+    assert np.array_equal(host(ug)[bmask], u0[bmask])
+    rb.close()
+
+
+def test_mg_solve_matches_composite_solution():
+    B, order = 8, 2
+    say("blocks multigrid solve B=8")
+    u0, _ = inputs.block_harmonic(B)
+    rb = RefinedBlocks(B, order, device=DEV)
+    f = torch.zeros(u0.shape, dtype=torch.float64, device=DEV)
+    ug = torch.from_numpy(u0).to(DEV)
+    r0 = np.sqrt(rb.residual_norm2(f, ug))
+    ug, info = rb.mg_solve(f, ug, tol=1e-11 * r0)
+    say(f"  cycles={info.cycles} residual={info.relres:.3e}")
+    assert info.converged and info.cycles <= 20
+    uo = composite(B, order)
+    assert np.abs(host(ug)[:, 1:-1, 1:-1, 1:-1] - uo).max() <= 1e-8 * np.abs(uo).max()
+    # a cycle limit that is too small is reported, with the iterate kept
+    rb2 = RefinedBlocks(B, order, max_cycles=2, device=DEV)
+    u2 = torch.from_numpy(inputs.block_harmonic(B)[0]).to(DEV)
+    u2, info2 = rb2.mg_solve(f, u2, tol=1e-11 * r0)
+    assert not info2.converged and info2.cycles == 2 and 0 < info2.relres < r0
+    rb.close()
+    rb2.close()
+
+
+def mg_error(B, order):
+    """Sect. 5's run: V(3,3)-cycles until the L2 residual norm is below 1e-16 or 35 cycles,
+    then the volume-weighted L2 error against Eq. 2's exact solution."""
+    u0, exact = inputs.block_harmonic(B)
+    rb = RefinedBlocks(B, order, device=DEV)
+    f = torch.zeros(u0.shape, dtype=torch.float64, device=DEV)
+    ug = torch.from_numpy(u0).to(DEV)
+    ug, info = rb.mg_solve(f, ug, tol=1e-16)
+    u = host(ug)
+    rb.close()
+    hb = np.array([w / B for (_, _, w) in inputs.block_list()])
+    e = (u - exact)[:, 1:-1, 1:-1, 1:-1].reshape(120, -1)
+    return float(np.sqrt(np.sum(hb ** 3 * np.sum(e ** 2, axis=1)))), info
+
+
+def test_table1_pattern_with_multigrid():
+    """Table 1's experiment with the paper's solver at its smallest block sizes (16, 32, 64):
+    constant C2F does not converge (kappa ~ 1), linear C2F is first order (kappa rising
+    towards 0.5), quadratic C2F second order (kappa within Table 1's deviation from 0.25)."""
+    e = {}
+    for order in (0, 1, 2):
+        for B in (16, 32, 64):
+            e[(order, B)], info = mg_error(B, order)
+            say(f"  order {order} B={B}: L2 error {e[(order, B)]:.4e} ({info.cycles} cycles, "
+                f"residual {info.relres:.2e})")
+            assert info.cycles == 35
+    k = {o: (e[(o, 32)] / e[(o, 16)], e[(o, 64)] / e[(o, 32)]) for o in (0, 1, 2)}
+    say(f"  kappa {k}")
+    assert all(abs(x - 1.0) <= 0.05 for x in k[0])
+    assert 0.4 <= k[1][0] <= k[1][1] <= 0.55
+    assert all(abs(x - 0.25) <= 0.011 for x in k[2])
