@@ -22,9 +22,11 @@ Also reported:
     L2 error of the harmonic problem (Eq. 1-2) at 256^3 and 512^3 cells with its
     grid-convergence ratio kappa (Eq. 3).  --no-fv skips it;
   - the 2:1 refined block layout of Sect. 5 ("refined_blocks", 56 + 64 blocks): time of the
-    ghost exchange (Sect. 3: same-level, F2C, quadratic C2F) and of a composite Jacobi sweep
-    at 64^3 cells per block, and kappa (Eq. 3) from GPU solves at 8^3 and 16^3 cells per block
-    with quadratic C2F (Table 1's second-order column).  --no-blocks skips it.
+    ghost exchange (Sect. 3: same-level, F2C, quadratic C2F), of a composite Jacobi sweep and
+    of a V(3,3) cycle of Sect. 5's multigrid at 64^3 and 128^3 cells per block, and Table 1
+    from GPU solves (35 V(3,3)-cycles, the paper's stopping rule) for constant, linear and
+    quadratic C2F at 16^3 ... 128^3 cells per block (--table1-max 256 adds the paper's largest
+    size), with kappa (Eq. 3) and the paper's values beside them.  --no-blocks skips it.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fv] [--n 513]
 
@@ -262,7 +264,37 @@ def fv_benchmark(dev, copy_gbs: float, N: int = 512, cycles: int = 100):
     }
 
 
-def refined_benchmark(dev, B: int = 64):
+# Sect. 5, Table 1: L2 error norm per block size for the constant, first- and second-order
+# C2F schemes (the paper's printed values, for comparison only)
+PAPER_TABLE1 = {
+    0: {16: 0.235, 32: 0.227, 64: 0.224, 128: 0.222, 256: 0.221},
+    1: {16: 1.067e-2, 32: 5.255e-3, 64: 2.611e-3, 128: 1.302e-3, 256: 6.499e-4},
+    2: {16: 3.017e-3, 32: 7.215e-4, 64: 1.764e-4, 128: 4.361e-5, 256: 1.084e-5},
+}
+
+
+def _block_l2_error(u, B):
+    """Volume-weighted L2 error sqrt(sum_b h_b^3 sum (u - u_exact)^2) of a refined-layout
+    solution tensor against Eq. 2's exact solution at the inner cell centres (on u's device)."""
+    import math
+
+    import torch
+
+    from paper_2403_08063_amd import inputs
+
+    i = torch.arange(B, dtype=torch.float64, device=u.device) + 0.5
+    total = 0.0
+    for b, (_, idx, w) in enumerate(inputs.block_list()):
+        h = w / B
+        x, y, z = (idx[a] * w + i * h for a in range(3))
+        ex = (torch.sin(math.pi * x)[None, None, :] * torch.sin(math.pi * y)[None, :, None]
+              * torch.sinh(math.sqrt(2.0) * math.pi * z)[:, None, None])
+        d = u[b, 1:-1, 1:-1, 1:-1] - ex
+        total += h ** 3 * float(torch.sum(d * d))
+    return math.sqrt(total)
+
+
+def refined_benchmark(dev, B: int = 64, table_sizes=(16, 32, 64, 128)):
     """The refined block layout (see the module docstring)."""
     import numpy as np
     import torch
@@ -271,8 +303,7 @@ def refined_benchmark(dev, B: int = 64):
 
     rb = RefinedBlocks(B, 2, device=dev)
     stream = rb.stream
-    u0, _ = inputs.block_harmonic(B)
-    u = torch.from_numpy(u0).to(dev)
+    u = inputs.block_harmonic_device(B, dev)
     f = torch.zeros_like(u)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 50
@@ -295,38 +326,58 @@ def refined_benchmark(dev, B: int = 64):
     cells = 120 * B ** 3
     rb.close()
     del u, f
-    errs, sweeps, t_solve = {}, {}, {}
-    hb = None
-    for Bs in (8, 16):
-        u0, exact = inputs.block_harmonic(Bs)
-        r2 = RefinedBlocks(Bs, 2, device=dev)
-        fz = torch.zeros(u0.shape, dtype=torch.float64, device=dev)
-        ug = torch.from_numpy(u0).to(dev)
-        r0 = np.sqrt(r2.residual_norm2(fz, ug))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ug, info = r2.solve(fz, ug, tol=1e-11 * r0, check_every=2000)
-        torch.cuda.synchronize()
-        t_solve[Bs] = (time.perf_counter() - t0) * 1e3
-        hb = np.array([w / Bs for (_, _, w) in inputs.block_list()])
-        e = (ug.cpu().numpy() - exact)[:, 1:-1, 1:-1, 1:-1].reshape(120, -1)
-        errs[Bs] = float(np.sqrt(np.sum(hb ** 3 * np.sum(e ** 2, axis=1))))
-        sweeps[Bs] = info.cycles
-        r2.close()
+    # one V(3,3)-cycle (256 coarsest iterations), 5 cycles timed after one
+    t_cycle = {}
+    for Bv in (64, 128):
+        rv = RefinedBlocks(Bv, 2, device=dev)
+        uv = inputs.block_harmonic_device(Bv, dev)
+        fv = torch.zeros_like(uv)
+        rv.vcycle(fv, uv)
+        ev0.record(rv.stream)
+        for _ in range(5):
+            rv.vcycle(fv, uv)
+        ev1.record(rv.stream)
+        ev1.synchronize()
+        t_cycle[Bv] = ev0.elapsed_time(ev1) / 5
+        rv.close()
+        del uv, fv
+    # Table 1: 35 cycles (L2 residual 1e-16 is below rounding), L2 error per block size
+    errs, t_solve, cyc = {0: {}, 1: {}, 2: {}}, {0: {}, 1: {}, 2: {}}, {0: {}, 1: {}, 2: {}}
+    for order in (0, 1, 2):
+        for Bs in table_sizes:
+            r2 = RefinedBlocks(Bs, order, device=dev)
+            ug = inputs.block_harmonic_device(Bs, dev)
+            fz = torch.zeros_like(ug)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ug, info = r2.mg_solve(fz, ug, tol=1e-16)
+            torch.cuda.synchronize()
+            t_solve[order][Bs] = (time.perf_counter() - t0) * 1e3
+            cyc[order][Bs] = info.cycles
+            errs[order][Bs] = _block_l2_error(ug, Bs)
+            r2.close()
+            del ug, fz
+            print(f"bench: refined blocks order {order} B={Bs}: L2 error {errs[order][Bs]:.4e} "
+                  f"({info.cycles} cycles, {t_solve[order][Bs]:.0f} ms)", file=sys.stderr, flush=True)
+    kappa = {o: {f"{a}->{b}": round(errs[o][b] / errs[o][a], 4)
+                 for a, b in zip(table_sizes[:-1], table_sizes[1:])} for o in (0, 1, 2)}
     return {
         "workload": f"2:1 refined layout of [0,1]^3 (56 level-2 + 64 level-3 blocks), {B}^3 cells "
-                    "per block, quadratic C2F / linear F2C ghost exchange, damped Jacobi",
+                    "per block, quadratic C2F / linear F2C ghost exchange, damped Jacobi; "
+                    "V(3,3) multigrid down to 4^3 cells per block",
         "cells": cells,
         "ghost_fill_ms": round(t_fill, 4),
         "ghost_cells_per_fill": 120 * 6 * B * B,
         "jacobi_sweep_with_fill_ms": round(t_sweep, 4),
         "jacobi_glups": round(cells / (t_sweep * 1e-3) / 1e9, 1),
         "jacobi_algorithmic_gbs": round(24 * cells / (t_sweep * 1e-3) / 1e9, 1),
-        "harmonic_l2_error": {str(k): v for k, v in errs.items()},
-        "harmonic_jacobi_sweeps": {str(k): v for k, v in sweeps.items()},
-        "harmonic_solve_ms": {str(k): round(v, 1) for k, v in t_solve.items()},
-        "kappa_8_16": round(errs[16] / errs[8], 4),
-        "paper_table1_l2_error_block16": 3.017e-3,
+        "vcycle_ms": {str(k): round(v, 3) for k, v in t_cycle.items()},
+        "table1_l2_error": {str(o): {str(b): v for b, v in errs[o].items()} for o in errs},
+        "table1_kappa": {str(o): kappa[o] for o in kappa},
+        "table1_cycles": {str(o): {str(b): v for b, v in cyc[o].items()} for o in cyc},
+        "table1_solve_ms": {str(o): {str(b): round(v, 1) for b, v in t_solve[o].items()} for o in t_solve},
+        "paper_table1_l2_error": {str(o): {str(b): PAPER_TABLE1[o][b] for b in table_sizes if b in PAPER_TABLE1[o]}
+                                  for o in PAPER_TABLE1},
     }
 
 
@@ -390,6 +441,8 @@ def main():
     ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--blocks-only", action="store_true",
                     help="run only the refined-block leg, print its record")
+    ap.add_argument("--table1-max", type=int, default=128, choices=(64, 128, 256),
+                    help="largest block size of the refined-layout Table 1 run")
     ap.add_argument("--fv-only", action="store_true",
                     help="run only the paper-benchmark (cell-centred FV) leg, print its record")
     ap.add_argument("--pmc-sample", action="store_true")
@@ -405,10 +458,11 @@ def main():
     if args.pmc_sample:
         pmc_sample(args.n)
         return
+    table_sizes = tuple(b for b in (16, 32, 64, 128, 256) if b <= args.table1_max)
     if args.blocks_only:
         import torch
 
-        print(json.dumps(refined_benchmark(torch.device("cuda:0"))), flush=True)
+        print(json.dumps(refined_benchmark(torch.device("cuda:0"), table_sizes=table_sizes)), flush=True)
         return
     if args.fv_only:
         import torch
@@ -598,9 +652,10 @@ def main():
               f"{rec['fv_benchmark']['vcycle_ms']} ms", file=sys.stderr, flush=True)
     if not args.no_blocks:
         print("bench: refined block layout (Sect. 3/5)", file=sys.stderr, flush=True)
-        rec["refined_blocks"] = refined_benchmark(dev)
-        print(f"bench: refined blocks fill {rec['refined_blocks']['ghost_fill_ms']} ms, kappa "
-              f"{rec['refined_blocks']['kappa_8_16']}", file=sys.stderr, flush=True)
+        rec["refined_blocks"] = refined_benchmark(dev, table_sizes=table_sizes)
+        print(f"bench: refined blocks fill {rec['refined_blocks']['ghost_fill_ms']} ms, V(3,3) "
+              f"{rec['refined_blocks']['vcycle_ms']} ms, kappa (quadratic) "
+              f"{rec['refined_blocks']['table1_kappa']['2']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(f_np, levels, info64.cycles)

@@ -163,6 +163,37 @@ def block_harmonic(B: int):
     return u0, exact
 
 
+def block_harmonic_device(B: int, device):
+    """block_harmonic's u0 built block by block with torch on `device` (the position array of
+    block_harmonic would not fit the host at the largest block sizes): the Dirichlet data of
+    Eq. 2 at the face centres of the domain-boundary ghosts, 0 elsewhere."""
+    import torch
+
+    m = B + 2
+    u0 = torch.zeros((120, m, m, m), dtype=torch.float64, device=device)
+    i = torch.arange(m, dtype=torch.float64, device=device) - 0.5
+    for b, (lv, idx, w) in enumerate(block_list()):
+        per = 4 if lv == 2 else 8
+        h = w / B
+        c = []
+        for a in range(3):
+            ca = idx[a] * w + i * h
+            if idx[a] == 0:
+                ca[0] = 0.0
+            if idx[a] == per - 1:
+                ca[-1] = 1.0
+            c.append(ca)
+        val = (torch.sin(np.pi * c[0])[None, None, :] * torch.sin(np.pi * c[1])[None, :, None]
+               * torch.sinh(np.sqrt(2.0) * np.pi * c[2])[:, None, None])
+        for a in range(3):
+            for k, on in ((0, idx[a] == 0), (m - 1, idx[a] == per - 1)):
+                if on:
+                    sl = [slice(None)] * 3
+                    sl[2 - a] = k
+                    u0[b][tuple(sl)] = val[tuple(sl)]
+    return u0
+
+
 def gaussian_random_field(dim: int, n: int, seed: int, corr: float = 0.1,
                           sigma: float = 1.0) -> np.ndarray:
     """Stationary Gaussian field with covariance sigma^2 exp(-r^2 / (2 corr^2)).
