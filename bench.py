@@ -143,7 +143,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, n: int):
 
 
 def _short_kernel_name(name: str) -> str:
-    name = name.replace("void ", "").replace("mgk::(anonymous namespace)::", "")
+    name = name.replace("void ", "").replace("mgk::", "").replace("(anonymous namespace)::", "")
     depth, out = 0, []
     for ch in name:  # drop the argument list, keep template arguments
         if ch == "(" and depth == 0:
@@ -154,10 +154,11 @@ def _short_kernel_name(name: str) -> str:
     return "".join(out).strip()
 
 
-def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24):
+def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24, by_grid: bool = False):
     """Markdown summary of a `rocprofv3 --kernel-trace --stats` run of this script: the
     per-kernel table and the mean duration of the fine-level FP64 smoother launches (the
-    largest grid of k_rbgs_tiled<double, ...>), beside bench.py's own HIP-event figure."""
+    largest grid of k_rbgs_tiled<double, ...>), beside bench.py's own HIP-event figure;
+    by_grid adds a table per kernel and launch grid (the levels of a multigrid run)."""
     import csv
     import glob
 
@@ -193,6 +194,17 @@ def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24):
                     head[-1] += (f" (bench.py's HIP-event average per launch in the same run: "
                                  f"{rec['roofline']['launch_ms'] * 1e3:.1f} us)")
         head[-1] += "."
+    if by_grid:
+        agg = {}
+        for r in csv.DictReader(open(trace[0])):
+            key = (_short_kernel_name(r["Kernel_Name"]),
+                   f"{r['Grid_Size_X']}x{r['Grid_Size_Y']}x{r['Grid_Size_Z']}")
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            n, t = agg.get(key, (0, 0.0))
+            agg[key] = (n + 1, t + d)
+        lines += ["", "| kernel | grid (threads) | calls | total ms | avg us |", "|---|---|---:|---:|---:|"]
+        for (k, g), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+            lines.append(f"| `{k}` | {g} | {n} | {t / 1e3:.2f} | {t / n:.1f} |")
     print("\n".join(head + [""] + lines))
 
 
@@ -443,14 +455,19 @@ def main():
                     help="run only the refined-block leg, print its record")
     ap.add_argument("--table1-max", type=int, default=128, choices=(64, 128, 256),
                     help="largest block size of the refined-layout Table 1 run")
+    ap.add_argument("--blocks-vcycle-sample", type=int, default=0, metavar="B",
+                    help="run 5 V(3,3)-cycles of the refined-layout multigrid with B^3 cells per "
+                         "block after one warm-up cycle (a kernel-trace target), then exit")
     ap.add_argument("--fv-only", action="store_true",
                     help="run only the paper-benchmark (cell-centred FV) leg, print its record")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", nargs="+", metavar=("TRACE_DIR", "BENCH_LOG"))
+    ap.add_argument("--by-grid", action="store_true",
+                    help="with --summarize-trace: add a table per kernel and launch grid")
     args = ap.parse_args()
     if args.summarize_trace:
-        summarize_trace(*args.summarize_trace[:2])
+        summarize_trace(*args.summarize_trace[:2], by_grid=args.by_grid)
         return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.n)
@@ -459,6 +476,21 @@ def main():
         pmc_sample(args.n)
         return
     table_sizes = tuple(b for b in (16, 32, 64, 128, 256) if b <= args.table1_max)
+    if args.blocks_vcycle_sample:
+        import torch
+
+        from paper_2403_08063_amd import RefinedBlocks, inputs
+
+        dev = torch.device("cuda:0")
+        Bv = args.blocks_vcycle_sample
+        rv = RefinedBlocks(Bv, 2, device=dev)
+        uv = inputs.block_harmonic_device(Bv, dev)
+        fv = torch.zeros_like(uv)
+        for _ in range(6):
+            rv.vcycle(fv, uv)
+        torch.cuda.synchronize()
+        print(f"bench: 6 block V-cycles at B={Bv} done", flush=True)
+        return
     if args.blocks_only:
         import torch
 

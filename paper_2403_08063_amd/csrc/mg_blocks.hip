@@ -267,11 +267,12 @@ __device__ __forceinline__ size_t bidx(int m, int b, int z, int y, int x)
 }
 
 // (x, y, z) from the index along axis ax and the two tangential indices (increasing axes)
+// (selects, not stores through a reference chosen by ax: those end up in per-lane scratch)
 __device__ __forceinline__ void face_coords(int ax, int n, int t1, int t2, int& x, int& y, int& z)
 {
-  if (ax == 0) { x = n; y = t1; z = t2; }
-  else if (ax == 1) { y = n; x = t1; z = t2; }
-  else { z = n; x = t1; y = t2; }
+  x = ax == 0 ? n : t1;
+  y = ax == 1 ? n : (ax == 0 ? t1 : t2);
+  z = ax == 2 ? n : t2;
 }
 
 // first tangential base (offset from coarse index T, 0-based in [0, B)) for the fine position
@@ -290,28 +291,17 @@ __device__ __forceinline__ int tangential_first(int order, int T, int B, int t)
   return -1;
 }
 
-constexpr int kFillThreads = 256;
-
-__global__ void __launch_bounds__(kFillThreads)
-    k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
+// value of the interface ghost cell (t1, t2) of face (ax, side) with face-table entry e (kind
+// same, F2C or C2F), from the neighbouring blocks' inner cells read through rd(b, z, y, x)
+template <class Rd>
+__device__ __forceinline__ double interface_ghost(const Rd& rd, int B, int order, const C2FWeights& W,
+                                                  const int* e, int ax, int side, int t1, int t2)
 {
-  const int m = B + 2;
-  const int q = blockIdx.x * kFillThreads + threadIdx.x;  // ghost cell of the face
-  if (q >= B * B) return;
-  const int f = blockIdx.y, b = blockIdx.z;
-  const int ax = f >> 1, side = f & 1;
-  const int* e = faces + ((size_t)b * 6 + f) * kFaceInts;
   const int kind = e[0];
-  if (kind == kFaceBoundary) return;
-  const int t1 = 1 + q % B, t2 = 1 + q / B;
-  int gx, gy, gz;
-  face_coords(ax, side ? B + 1 : 0, t1, t2, gx, gy, gz);
-  const size_t gi = bidx(m, b, gz, gy, gx);
   if (kind == kFaceSame) {
     int x, y, z;
     face_coords(ax, side ? 1 : B, t1, t2, x, y, z);
-    u[gi] = u[bidx(m, e[1], z, y, x)];
-    return;
+    return rd(e[1], z, y, x);
   }
   const int half = B / 2;
   if (kind == kFaceF2C) {
@@ -325,10 +315,9 @@ __global__ void __launch_bounds__(kFillThreads)
         for (int d1 = 0; d1 < 2; ++d1) {
           int x, y, z;
           face_coords(ax, li ? l1 : l0, f1 + d1, f2 + d2, x, y, z);
-          s += 0.125 * u[bidx(m, fb, z, y, x)];
+          s += 0.125 * rd(fb, z, y, x);
         }
-    u[gi] = s;
-    return;
+    return s;
   }
   // C2F: coarse cell (T1, T2) of the quadrant and the fine position in it
   const int cb = e[1];
@@ -345,9 +334,27 @@ __global__ void __launch_bounds__(kFillThreads)
       for (int j1 = 0; j1 < cn; ++j1) {
         int x, y, z;
         face_coords(ax, ci + away * a, T1 + 1 + a1 + j1, T2 + 1 + a2 + j2, x, y, z);
-        s += W.wn[a] * w2[j2] * w1[j1] * u[bidx(m, cb, z, y, x)];
+        s += W.wn[a] * w2[j2] * w1[j1] * rd(cb, z, y, x);
       }
-  u[gi] = s;
+  return s;
+}
+
+constexpr int kFillThreads = 256;
+
+__global__ void __launch_bounds__(kFillThreads)
+    k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
+{
+  const int m = B + 2;
+  const int q = blockIdx.x * kFillThreads + threadIdx.x;  // ghost cell of the face
+  if (q >= B * B) return;
+  const int f = blockIdx.y, b = blockIdx.z;
+  const int* e = faces + ((size_t)b * 6 + f) * kFaceInts;
+  if (e[0] == kFaceBoundary) return;
+  const int t1 = 1 + q % B, t2 = 1 + q / B;
+  int gx, gy, gz;
+  face_coords(f >> 1, (f & 1) ? B + 1 : 0, t1, t2, gx, gy, gz);
+  auto rd = [&](int bb, int z, int y, int x) { return u[bidx(m, bb, z, y, x)]; };
+  u[bidx(m, b, gz, gy, gx)] = interface_ghost(rd, B, order, W, e, f >> 1, f & 1, t1, t2);
 }
 
 // (A u) at inner cell (z, y, x) of block b: ghost neighbours on the domain boundary as
@@ -375,15 +382,49 @@ __device__ __forceinline__ double blk_apply_at(int B, const int* __restrict__ fb
   return s * ih2;
 }
 
-constexpr int kJacThreads = 64;
+// One thread per inner cell of all blocks of size B, 256 threads per workgroup: for B >= 64
+// a workgroup covers 64 x 4 cells of an (x, y) plane (grid: x tiles, y tiles, blocks x B
+// planes); for smaller blocks a flat index over the blocks' cells (B^3 >= 64 cells a block).
+constexpr int kCellThreads = 256;
+constexpr int kCellRowsMin = 64;
 
-__global__ void __launch_bounds__(kJacThreads)
+dim3 cell_grid(int B)
+{
+  if (B >= kCellRowsMin) return dim3((unsigned)((B + 63) / 64), (unsigned)((B + 3) / 4), (unsigned)(kBlocks * B));
+  const size_t cells = (size_t)kBlocks * B * B * B;
+  return dim3((unsigned)((cells + kCellThreads - 1) / kCellThreads), 1, 1);
+}
+
+// 1-based inner coordinates of this thread's cell; false past the end
+__device__ __forceinline__ bool cell_of(int B, int& b, int& z, int& y, int& x)
+{
+  if (B >= kCellRowsMin) {
+    x = 1 + blockIdx.x * 64 + (threadIdx.x & 63);
+    y = 1 + blockIdx.y * 4 + (threadIdx.x >> 6);
+    b = blockIdx.z / B;
+    z = 1 + blockIdx.z % B;
+    return x <= B && y <= B;
+  }
+  const int n2 = B * B, n3 = n2 * B;
+  const int t = blockIdx.x * kCellThreads + threadIdx.x;
+  if (t >= kBlocks * n3) return false;
+  b = t / n3;
+  int r = t - b * n3;
+  const int zz = r / n2;
+  r -= zz * n2;
+  const int yy = r / B;
+  z = 1 + zz;
+  y = 1 + yy;
+  x = 1 + r - yy * B;
+  return true;
+}
+
+__global__ void __launch_bounds__(kCellThreads)
     k_blk_jacobi(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
                  const double* __restrict__ f, const double* __restrict__ u, double* __restrict__ uout)
 {
-  const int x = 1 + blockIdx.x * kJacThreads + threadIdx.x, y = 1 + blockIdx.y;
-  const int b = blockIdx.z / B, z = 1 + blockIdx.z % B;
-  if (x > B) return;
+  int b, z, y, x;
+  if (!cell_of(B, b, z, y, x)) return;
   const int m = B + 2;
   const double h = hs[b];
   const size_t i = bidx(m, b, z, y, x);
@@ -430,19 +471,20 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- multigrid transfers
-constexpr int kXferThreads = 64;
-
 // fc = mean of the 8 children's residuals f - A u (children in z, y, x order) for every coarse
-// inner cell; uc (optional) = 0 there.  B: fine block size, u's ghosts filled.
-__global__ void __launch_bounds__(kXferThreads)
+// inner cell; uc (optional) = 0 there.  B: fine block size, u's ghosts filled; one thread per
+// coarse cell (cell_grid(B / 2)).
+__global__ void __launch_bounds__(kCellThreads)
     k_blk_restrict(int B, const int* __restrict__ faces, const double* __restrict__ hs,
                    const double* __restrict__ f, const double* __restrict__ u,
                    double* __restrict__ fc, double* __restrict__ uc)
 {
   const int Bc = B / 2;
-  const int X = blockIdx.x * kXferThreads + threadIdx.x, Y = blockIdx.y;
-  const int b = blockIdx.z / Bc, Z = blockIdx.z % Bc;
-  if (X >= Bc) return;
+  int b, Z, Y, X;
+  if (!cell_of(Bc, b, Z, Y, X)) return;
+  --Z;
+  --Y;
+  --X;  // 0-based coarse indices
   const int m = B + 2;
   const double h = hs[b];
   const double ih2 = 1.0 / (h * h);
@@ -467,13 +509,13 @@ __global__ void __launch_bounds__(kXferThreads)
 // filled).  A fine cell lies towards +1 along an axis where its 0-based index is odd, -1
 // where even; its correction is (e_P + e_x + e_y + e_z) / 4 with e_a the parent's neighbour on
 // that side along axis a, -e_P where that neighbour lies across the domain boundary.
-__global__ void __launch_bounds__(kXferThreads)
+__global__ void __launch_bounds__(kCellThreads)
     k_blk_prolong(int B, const int* __restrict__ faces, const double* __restrict__ e,
                   double* __restrict__ u)
 {
-  const int x0 = blockIdx.x * kXferThreads + threadIdx.x, y0 = blockIdx.y;
-  const int b = blockIdx.z / B, z0 = blockIdx.z % B;  // 0-based fine inner indices
-  if (x0 >= B) return;
+  int b, z1, y1, x1;
+  if (!cell_of(B, b, z1, y1, x1)) return;
+  const int x0 = x1 - 1, y0 = y1 - 1, z0 = z1 - 1;  // 0-based fine inner indices
   const int Bc = B / 2, mc = Bc + 2;
   const int* fb = faces + (size_t)b * 6 * kFaceInts;
   const int X = 1 + x0 / 2, Y = 1 + y0 / 2, Z = 1 + z0 / 2;
@@ -525,10 +567,10 @@ double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, i
 {
   const BlkLevel& L = c->lv[l];
   const int B = L.B;
-  const dim3 grid((unsigned)((B + kJacThreads - 1) / kJacThreads), B, kBlocks * B);
+  const dim3 grid = cell_grid(B);
   for (int s = 0; s < count; ++s) {
     fill(c, l, cur);
-    k_blk_jacobi<<<grid, kJacThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth);
+    k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth);
     double* x = cur;
     cur = oth;
     oth = x;
@@ -542,8 +584,7 @@ void restrict_residual(mgblk_ctx* c, int l, const double* f, double* u, double* 
   const BlkLevel& L = c->lv[l];
   const int Bc = L.B / 2;
   fill(c, l, u);
-  const dim3 grid((unsigned)((Bc + kXferThreads - 1) / kXferThreads), Bc, kBlocks * Bc);
-  k_blk_restrict<<<grid, kXferThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc);
+  k_blk_restrict<<<cell_grid(Bc), kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc);
 }
 
 // fills ec's interface ghosts (level l+1), then u (level l) += P ec
@@ -551,8 +592,7 @@ void prolong_correct(mgblk_ctx* c, int l, double* ec, double* u)
 {
   const int B = c->lv[l].B;
   fill(c, l + 1, ec);
-  const dim3 grid((unsigned)((B + kXferThreads - 1) / kXferThreads), B, kBlocks * B);
-  k_blk_prolong<<<grid, kXferThreads, 0, c->s>>>(B, c->faces, ec, u);
+  k_blk_prolong<<<cell_grid(B), kCellThreads, 0, c->s>>>(B, c->faces, ec, u);
 }
 
 // V(nu1, nu2) on level l from the iterate in x (y: the level's second buffer); returns the
