@@ -35,6 +35,9 @@ EXPORTS = [
     "mgblk_last_error", "mgblk_fill", "mgblk_jacobi", "mgblk_residual_norm2", "mgblk_solve",
     "mgblk_levels", "mgblk_smooth", "mgblk_restrict_residual", "mgblk_prolong_correct",
     "mgblk_vcycle", "mgblk_mg_solve",
+    # include/mg_galerkin.h
+    "mggal_workspace_bytes", "mggal_setup", "mggal_destroy", "mggal_last_error", "mggal_stencil",
+    "mggal_vcycle", "mggal_solve",
 ]
 
 
@@ -54,6 +57,11 @@ class MgBlkGrid(ctypes.Structure):
     _fields_ = [("B", ctypes.c_int), ("order", ctypes.c_int), ("omega", ctypes.c_double),
                 ("levels", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("coarse_iters", ctypes.c_int), ("max_cycles", ctypes.c_int)]
+
+
+class MgGalGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int)]
 
 
 class MgError(RuntimeError):
@@ -78,6 +86,7 @@ def lib() -> ctypes.CDLL:
     G = ctypes.POINTER(MgGrid)
     FG = ctypes.POINTER(MgFvGrid)
     BG = ctypes.POINTER(MgBlkGrid)
+    GG = ctypes.POINTER(MgGalGrid)
     PI, PD = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     sig = {
         "mg_validate": (i, [G]),
@@ -127,6 +136,13 @@ def lib() -> ctypes.CDLL:
         "mgblk_prolong_correct": (i, [P, i, P, P]),
         "mgblk_vcycle": (i, [P, P, P]),
         "mgblk_mg_solve": (i, [P, P, P, d, PI, PD]),
+        "mggal_workspace_bytes": (S, [GG]),
+        "mggal_setup": (i, [GG, P, P, S, P, ctypes.POINTER(P)]),
+        "mggal_destroy": (None, [P]),
+        "mggal_last_error": (ctypes.c_char_p, [P]),
+        "mggal_stencil": (i, [P, i, P]),
+        "mggal_vcycle": (i, [P, P, P]),
+        "mggal_solve": (i, [P, P, P, d, PI, PD]),
     }
     for name in EXPORTS:
         res, args = sig[name]
@@ -160,5 +176,13 @@ def check_blk(status: int, ctx=None, allow=()) -> int:
     """check() for the refined-block contexts (their own error text)."""
     if status != MG_OK and status not in allow:
         msg = lib().mgblk_last_error(ctx)
+        raise MgError(status, msg.decode() if msg else "")
+    return status
+
+
+def check_gal(status: int, ctx=None, allow=()) -> int:
+    """check() for the Galerkin-coarsening contexts (their own error text)."""
+    if status != MG_OK and status not in allow:
+        msg = lib().mggal_last_error(ctx)
         raise MgError(status, msg.decode() if msg else "")
     return status

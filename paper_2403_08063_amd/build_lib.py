@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_api.hip", "mg_fv.hip", "mg_blocks.hip", "mg_kernels.hip", "mg_smooth_tiled.hip", "mg_resid_tiled.hip",
-           "mg_tail.hip"]
+SOURCES = ["mg_api.hip", "mg_fv.hip", "mg_blocks.hip", "mg_galerkin.hip", "mg_kernels.hip", "mg_smooth_tiled.hip",
+           "mg_resid_tiled.hip", "mg_tail.hip"]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

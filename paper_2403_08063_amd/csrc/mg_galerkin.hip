@@ -1,0 +1,398 @@
+// Galerkin coarsening of the variable-coefficient operator behind the C ABI of
+// include/mg_galerkin.h.  Level 0 runs the 7-point kernels of mg_kernels.hip (red-black
+// Gauss-Seidel with face coefficients, residual + full weighting, trilinear prolongation,
+// norms); the coarse levels hold 27-point stencils built on the GPU by probing R A P with
+// combs of coarse nodes, and run the kernels below: eight-colour Gauss-Seidel, residual with
+// full weighting, and the exact solve of the one-node coarsest level.
+#include "../../include/mg_galerkin.h"
+#include "mg_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr size_t kGalAlign = 256;
+constexpr int kGalThreads = 256;
+constexpr int kCentre = 13;  // stencil array of the node itself: 9 + 3 + 1
+
+thread_local char g_gal_err[512] = "no error";
+
+__device__ __forceinline__ size_t gidx(int n, int z, int y, int x)
+{
+  return ((size_t)z * n + y) * (size_t)n + x;
+}
+
+// (A u)_i - a_ii u_i: the off-diagonal part of the 27-point stencil at interior node i
+__device__ __forceinline__ double offdiag(const double* __restrict__ S, size_t cnt,
+                                          const double* __restrict__ u, int n, int z, int y,
+                                          int x, size_t i)
+{
+  double s = 0.0;
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    if (o == kCentre) continue;
+    const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+    s += S[o * cnt + i] * u[gidx(n, z + dz, y + dy, x + dx)];
+  }
+  return s;
+}
+
+// one colour of eight-colour Gauss-Seidel: nodes with parities (pz, py, px) of colour c
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_gs(int n, const double* __restrict__ S, const double* __restrict__ f, double* u, int c)
+{
+  const int half = (n - 1) / 2;
+  const int t = blockIdx.x * kGalThreads + threadIdx.x;
+  if (t >= half * half * half) return;
+  const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
+  // interior index with parity p: 2 j + 2 - p  (p = 1: 1, 3, ..; p = 0: 2, 4, ..)
+  const int x = 2 * (t % half) + 2 - px, y = 2 * ((t / half) % half) + 2 - py, z = 2 * (t / (half * half)) + 2 - pz;
+  if (x > n - 2 || y > n - 2 || z > n - 2) return;
+  const size_t cnt = (size_t)n * n * n;
+  const size_t i = gidx(n, z, y, x);
+  u[i] = (f[i] - offdiag(S, cnt, u, n, z, y, x, i)) / S[kCentre * cnt + i];
+}
+
+// fc = FW(f - A u) at coarse interior nodes (nf: fine nodes per side; f == nullptr reads 0)
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_restrict(int nf, const double* __restrict__ S, const double* __restrict__ f,
+                   const double* __restrict__ u, double* __restrict__ fc)
+{
+  const int nc = (nf - 1) / 2 + 1, m = nc - 2;
+  const int t = blockIdx.x * kGalThreads + threadIdx.x;
+  if (t >= m * m * m) return;
+  const int X = 1 + t % m, Y = 1 + (t / m) % m, Z = 1 + t / (m * m);
+  const size_t cnt = (size_t)nf * nf * nf;
+  double s = 0.0;
+#pragma unroll 1
+  for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll 1
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int z = 2 * Z + oz, y = 2 * Y + oy, x = 2 * X + ox;  // always interior
+        const size_t i = gidx(nf, z, y, x);
+        const double au = S[kCentre * cnt + i] * u[i] + offdiag(S, cnt, u, nf, z, y, x, i);
+        const double r = (f ? f[i] : 0.0) - au;
+        const double w = (oz ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (ox ? 0.25 : 0.5);
+        s += w * r;
+      }
+  fc[gidx(nc, Z, Y, X)] = s;
+}
+
+// e = the comb of residue class (cz, cy, cx): 1 at interior nodes J with J_a = c_a mod 3
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_comb(int n, int cz, int cy, int cx, double* __restrict__ e)
+{
+  const size_t t = (size_t)blockIdx.x * kGalThreads + threadIdx.x;
+  const size_t cnt = (size_t)n * n * n;
+  if (t >= cnt) return;
+  const int x = (int)(t % n), y = (int)((t / n) % n), z = (int)(t / ((size_t)n * n));
+  const bool in = x > 0 && y > 0 && z > 0 && x < n - 1 && y < n - 1 && z < n - 1;
+  e[t] = in && x % 3 == cx && y % 3 == cy && z % 3 == cz ? 1.0 : 0.0;
+}
+
+// S[o][I] = -fc[I] at coarse interior nodes, o the offset to I's neighbour of class c
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_scatter(int nc, int cz, int cy, int cx, const double* __restrict__ fc,
+                  double* __restrict__ S)
+{
+  const int m = nc - 2;
+  const int t = blockIdx.x * kGalThreads + threadIdx.x;
+  if (t >= m * m * m) return;
+  const int X = 1 + t % m, Y = 1 + (t / m) % m, Z = 1 + t / (m * m);
+  auto off = [](int c, int I) { const int r = ((c - I) % 3 + 3) % 3; return r == 2 ? -1 : r; };
+  const int o = 9 * (off(cz, Z) + 1) + 3 * (off(cy, Y) + 1) + (off(cx, X) + 1);
+  const size_t i = gidx(nc, Z, Y, X);
+  S[o * (size_t)nc * nc * nc + i] = -fc[i];
+}
+
+// the coarsest level (3^3 nodes): its one interior node
+__global__ void k_gal_coarsest(const double* __restrict__ S, const double* __restrict__ f,
+                               double* __restrict__ u)
+{
+  const size_t i = gidx(3, 1, 1, 1);
+  u[i] = f[i] / S[kCentre * 27 + i];
+}
+
+unsigned blocks_for(size_t count) { return (unsigned)((count + kGalThreads - 1) / kGalThreads); }
+
+}  // namespace
+
+struct GalLevel {
+  int n = 0;
+  size_t cnt = 0;
+  double* u = nullptr;  // correction (levels >= 1)
+  double* f = nullptr;  // right-hand side (levels >= 1)
+  double* S = nullptr;  // 27 stencil arrays (levels >= 1)
+};
+
+struct mggal_ctx {
+  mggal_grid g{};
+  hipStream_t s = nullptr;
+  double h = 0;
+  double* k = nullptr;      // copy of the coefficient
+  double* probe = nullptr;  // level-0 probe vector
+  double* zero = nullptr;   // level-0 zero right-hand side (probing)
+  double* partial = nullptr;
+  double* scal = nullptr;
+  std::vector<GalLevel> lv;
+  char err[512] = "no error";
+};
+
+namespace {
+
+mg_status gal_fail(mggal_ctx* c, mg_status st, const char* fmt, ...)
+{
+  char* buf = c ? c->err : g_gal_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 512, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+mg_status gal_hip(mggal_ctx* c, hipError_t e, const char* what)
+{
+  if (e == hipSuccess) return MG_OK;
+  return gal_fail(c, MG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+mg_status gal_validate(const mggal_grid* g)
+{
+  if (!g) return gal_fail(nullptr, MG_EINVAL, "grid description is NULL");
+  const int n = g->n;
+  if (n < 5 || n > 1025 || ((n - 1) & (n - 2)) != 0)
+    return gal_fail(nullptr, MG_EINVAL, "n must be 2^m + 1 in [5, 1025] (got %d)", n);
+  int nl = n;
+  for (int l = 1; l < g->levels; ++l) nl = (nl - 1) / 2 + 1;
+  if (g->levels < 2 || nl != 3)
+    return gal_fail(nullptr, MG_EINVAL, "levels must reach 3 nodes per side (n=%d, levels=%d)", n, g->levels);
+  if (g->nu1 < 0 || g->nu2 < 0) return gal_fail(nullptr, MG_EINVAL, "nu1, nu2 must be >= 0");
+  if (g->max_cycles < 1) return gal_fail(nullptr, MG_EINVAL, "max_cycles must be >= 1");
+  return MG_OK;
+}
+
+struct GalCarver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count)
+  {
+    off = (off + kGalAlign - 1) / kGalAlign * kGalAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+void gal_layout(const mggal_grid* g, GalCarver& cv, mggal_ctx* c)
+{
+  const size_t cnt0 = (size_t)g->n * g->n * g->n;
+  double* k = cv.take<double>(cnt0);
+  double* probe = cv.take<double>(cnt0);
+  double* zero = cv.take<double>(cnt0);
+  double* partial = cv.take<double>(mgk::kNormBlocks);
+  double* scal = cv.take<double>(8);
+  std::vector<GalLevel> lv;
+  int n = g->n;
+  for (int l = 0; l < g->levels; ++l) {
+    GalLevel L;
+    L.n = n;
+    L.cnt = (size_t)n * n * n;
+    if (l > 0) {
+      L.u = cv.take<double>(L.cnt);
+      L.f = cv.take<double>(L.cnt);
+      L.S = cv.take<double>(27 * L.cnt);
+    }
+    lv.push_back(L);
+    n = (n - 1) / 2 + 1;
+  }
+  if (c) {
+    c->k = k;
+    c->probe = probe;
+    c->zero = zero;
+    c->partial = partial;
+    c->scal = scal;
+    c->lv = lv;
+  }
+}
+
+void smooth(mggal_ctx* c, int l, const double* f, double* u, int sweeps)
+{
+  const GalLevel& L = c->lv[l];
+  for (int s = 0; s < sweeps; ++s) {
+    if (l == 0) {
+      mgk::rbgs_colour<double>(c->s, 3, L.n, c->h, c->k, f, u, 0);
+      mgk::rbgs_colour<double>(c->s, 3, L.n, c->h, c->k, f, u, 1);
+    } else {
+      const int half = (L.n - 1) / 2;
+      for (int col = 0; col < 8; ++col)
+        k_gal_gs<<<blocks_for((size_t)half * half * half), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, col);
+    }
+  }
+}
+
+// fc (level l+1) = FW(f - A_l u); f == nullptr reads 0
+void restrict_to(mggal_ctx* c, int l, const double* f, const double* u, double* fc)
+{
+  const GalLevel& L = c->lv[l];
+  if (l == 0) {
+    mgk::restrict_residual<double>(c->s, 3, L.n, c->h, c->k, f ? f : c->zero, u, fc);
+  } else {
+    const size_t m = (size_t)c->lv[l + 1].n - 2;
+    k_gal_restrict<<<blocks_for(m * m * m), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, fc);
+  }
+}
+
+void vcycle_rec(mggal_ctx* c, int l, const double* f, double* u)
+{
+  const int last = (int)c->lv.size() - 1;
+  if (l == last) {
+    k_gal_coarsest<<<1, 1, 0, c->s>>>(c->lv[l].S, f, u);
+    return;
+  }
+  smooth(c, l, f, u, c->g.nu1);
+  GalLevel& C = c->lv[l + 1];
+  restrict_to(c, l, f, u, C.f);
+  mgk::fill<double>(c->s, C.cnt, 0.0, C.u);
+  vcycle_rec(c, l + 1, C.f, C.u);
+  mgk::prolong_add<double>(c->s, 3, C.n, C.u, u);
+  smooth(c, l, f, u, c->g.nu2);
+}
+
+// Galerkin operator of level l+1 by probing with the 27 combs of coarse nodes
+void build_level(mggal_ctx* c, int l)
+{
+  GalLevel& F = c->lv[l];
+  GalLevel& C = c->lv[l + 1];
+  double* w = l == 0 ? c->probe : F.u;  // fine probe vector (zero boundary)
+  mgk::fill<double>(c->s, 27 * C.cnt, 0.0, C.S);
+  const size_t m = (size_t)C.n - 2;
+  for (int cz = 0; cz < 3; ++cz)
+    for (int cy = 0; cy < 3; ++cy)
+      for (int cx = 0; cx < 3; ++cx) {
+        k_gal_comb<<<blocks_for(C.cnt), kGalThreads, 0, c->s>>>(C.n, cz, cy, cx, C.u);
+        mgk::fill<double>(c->s, F.cnt, 0.0, w);
+        mgk::prolong_add<double>(c->s, 3, C.n, C.u, w);
+        restrict_to(c, l, nullptr, w, C.f);
+        k_gal_scatter<<<blocks_for(m * m * m), kGalThreads, 0, c->s>>>(C.n, cz, cy, cx, C.f, C.S);
+      }
+}
+
+mg_status read_norm2(mggal_ctx* c, const double* f, const double* u, int mode, double* out)
+{
+  mgk::resid_norm2(c->s, 3, c->g.n, c->h, c->k, f, u, mode, c->partial, c->scal);
+  if (mg_status st = gal_hip(c, hipGetLastError(), "norm")) return st;
+  if (mg_status st = gal_hip(c, hipMemcpyAsync(out, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->s),
+                             "reading the norm"))
+    return st;
+  return gal_hip(c, hipStreamSynchronize(c->s), "stream synchronisation");
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+size_t mggal_workspace_bytes(const mggal_grid* grid)
+{
+  if (gal_validate(grid) != MG_OK) return 0;
+  GalCarver cv{nullptr};
+  gal_layout(grid, cv, nullptr);
+  return cv.off + kGalAlign;
+}
+
+mg_status mggal_setup(const mggal_grid* grid, const double* k, void* workspace, size_t bytes,
+                      void* stream, mggal_ctx** out)
+{
+  if (!out) return gal_fail(nullptr, MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (mg_status st = gal_validate(grid)) return st;
+  if (!k) return gal_fail(nullptr, MG_EINVAL, "k is NULL");
+  if (!workspace) return gal_fail(nullptr, MG_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kGalAlign != 0)
+    return gal_fail(nullptr, MG_EINVAL, "workspace must be %zu-byte aligned", kGalAlign);
+  const size_t need = mggal_workspace_bytes(grid);
+  if (bytes < need) return gal_fail(nullptr, MG_ENOMEM, "workspace of %zu bytes < %zu required", bytes, need);
+  mggal_ctx* c = new (std::nothrow) mggal_ctx;
+  if (!c) return gal_fail(nullptr, MG_ENOMEM, "host allocation of the context failed");
+  c->g = *grid;
+  c->s = static_cast<hipStream_t>(stream);
+  c->h = 1.0 / (grid->n - 1);
+  GalCarver cv{static_cast<char*>(workspace)};
+  gal_layout(grid, cv, c);
+  mgk::copy<double>(c->s, c->lv[0].cnt, k, c->k);
+  mgk::fill<double>(c->s, c->lv[0].cnt, 0.0, c->zero);
+  for (size_t l = 1; l < c->lv.size(); ++l) {  // zero boundaries of every coarse array
+    mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, c->lv[l].u);
+    mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, c->lv[l].f);
+  }
+  for (size_t l = 0; l + 1 < c->lv.size(); ++l) build_level(c, (int)l);
+  mg_status st = gal_hip(c, hipGetLastError(), "building the Galerkin hierarchy");
+  if (!st) st = gal_hip(c, hipStreamSynchronize(c->s), "setup");
+  if (st) {
+    snprintf(g_gal_err, sizeof g_gal_err, "%s", c->err);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return MG_OK;
+}
+
+void mggal_destroy(mggal_ctx* c) { delete c; }
+
+const char* mggal_last_error(const mggal_ctx* c) { return c ? c->err : g_gal_err; }
+
+mg_status mggal_stencil(mggal_ctx* c, int level, double* out)
+{
+  if (!c) return gal_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (level < 1 || level >= (int)c->lv.size()) return gal_fail(c, MG_EINVAL, "level %d has no stencil", level);
+  if (!out) return gal_fail(c, MG_EINVAL, "out is NULL");
+  mgk::copy<double>(c->s, 27 * c->lv[level].cnt, c->lv[level].S, out);
+  return gal_hip(c, hipGetLastError(), "copying the stencil");
+}
+
+mg_status mggal_vcycle(mggal_ctx* c, const double* f, double* u)
+{
+  if (!c) return gal_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (!f || !u) return gal_fail(c, MG_EINVAL, "f and u must be non-NULL");
+  vcycle_rec(c, 0, f, u);
+  return gal_hip(c, hipGetLastError(), "V-cycle");
+}
+
+mg_status mggal_solve(mggal_ctx* c, const double* f, double* u, double tol, int* cycles,
+                      double* relres)
+{
+  if (!c) return gal_fail(nullptr, MG_EINVAL, "context is NULL");
+  if (!f || !u) return gal_fail(c, MG_EINVAL, "f and u must be non-NULL");
+  if (!(tol > 0)) return gal_fail(c, MG_EINVAL, "tol must be > 0");
+  double b2 = 0, r2 = 0;
+  mg_status st = read_norm2(c, f, u, 1, &b2);
+  const double bn = std::sqrt(b2);
+  if (!st && !(bn > 0 && std::isfinite(bn))) st = gal_fail(c, MG_EINVAL, "right-hand side norm %.3e", bn);
+  int kcyc = 0;
+  double rel = 1.0;
+  if (!st) st = read_norm2(c, f, u, 0, &r2);
+  if (!st) rel = std::sqrt(r2) / bn;
+  while (!st && std::isfinite(rel) && rel > tol && kcyc < c->g.max_cycles) {
+    vcycle_rec(c, 0, f, u);
+    ++kcyc;
+    st = read_norm2(c, f, u, 0, &r2);
+    rel = std::sqrt(r2) / bn;
+  }
+  if (cycles) *cycles = kcyc;
+  if (relres) *relres = rel;
+  if (st) return st;
+  if (!std::isfinite(rel)) return gal_fail(c, MG_ENAN, "residual norm is not finite after %d cycles", kcyc);
+  if (rel > tol) return gal_fail(c, MG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", rel, tol, kcyc);
+  return MG_OK;
+}
+
+}  // extern "C"

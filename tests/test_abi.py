@@ -8,7 +8,7 @@ import re
 import pytest
 
 from paper_2403_08063_amd import _lib
-from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgBlkGrid, MgFvGrid, MgGrid
+from paper_2403_08063_amd._lib import MG_EINVAL, MG_OK, MgBlkGrid, MgFvGrid, MgGalGrid, MgGrid
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -20,7 +20,7 @@ def declared_functions():
             continue
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names |= set(re.findall(r"\b(mg(?:fv|blk)?_[a-z0-9_]+)\s*\(", text))
+        names |= set(re.findall(r"\b(mg(?:fv|blk|gal)?_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 
@@ -164,3 +164,35 @@ def test_blk_workspace_size():
     got = blk_bytes(B=B)
     assert want <= got <= want + 120 * 6 * 8 * 4 + 3 * 120 * 8 + 1024 * 8 + 8 * 256
     assert blk_bytes(B=B, levels=1) < got
+
+
+# ---------------------------------------------------------------- Galerkin coarsening
+def gal_bytes(**kw):
+    g = dict(n=33, levels=5, nu1=2, nu2=2, max_cycles=100)
+    g.update(kw)
+    return _lib.lib().mggal_workspace_bytes(ctypes.byref(MgGalGrid(**g)))
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(n=5, levels=2), dict(n=257, levels=8), dict(nu1=0)])
+def test_gal_valid_grids(kw):
+    assert gal_bytes(**kw) > 0
+
+
+@pytest.mark.parametrize("kw", [dict(n=32), dict(n=3, levels=1), dict(levels=4), dict(levels=6),
+                                dict(nu1=-1), dict(max_cycles=0), dict(n=2049, levels=11)])
+def test_gal_invalid_grids_need_no_workspace(kw):
+    assert gal_bytes(**kw) == 0
+
+
+def test_gal_workspace_size():
+    """Coefficient copy, probe and zero vectors on the fine level; correction, right-hand side
+    and 27 stencil arrays on every coarser level (256-byte aligned), plus partial sums."""
+    n, levels = 33, 5
+    al = lambda b: -(-b // 256) * 256  # noqa: E731
+    want = 3 * al(n ** 3 * 8)
+    nl = n
+    for _ in range(1, levels):
+        nl = (nl - 1) // 2 + 1
+        want += 2 * al(nl ** 3 * 8) + al(27 * nl ** 3 * 8)
+    got = gal_bytes(n=n, levels=levels)
+    assert want <= got <= want + 1024 * 8 + 4 * 256
