@@ -21,6 +21,9 @@ Also reported:
     time of a V(3,3) cycle over 100 cycles with 256 coarsest iterations (Sect. 6), and the
     L2 error of the harmonic problem (Eq. 1-2) at 256^3 and 512^3 cells with its
     grid-convergence ratio kappa (Eq. 3).  --no-fv skips it;
+  - Galerkin coarse operators ("galerkin") against the rediscretised hierarchy on the
+    lognormal-coefficient workloads at 257^3 and 513^3: setup, cycles and time of an FP64
+    solve to 1e-10.  --no-galerkin skips it;
   - the 2:1 refined block layout of Sect. 5 ("refined_blocks", 56 + 64 blocks): time of the
     ghost exchange (Sect. 3: same-level, F2C, quadratic C2F), of a composite Jacobi sweep and
     of a V(3,3) cycle of Sect. 5's multigrid at 64^3 and 128^3 cells per block, and Table 1
@@ -206,6 +209,59 @@ def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24, by_gri
         for (k, g), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
             lines.append(f"| `{k}` | {g} | {n} | {t / 1e3:.2f} | {t / n:.1f} |")
     print("\n".join(head + [""] + lines))
+
+
+def galerkin_benchmark(dev, sizes=((257, 8, 4), (513, 9, 5))):
+    """Galerkin against rediscretised coarse operators on the lognormal-coefficient workloads
+    (f = 1, k = exp(Gaussian random field)): setup (coefficient hierarchy / Galerkin
+    products), cycles and time of an FP64 solve to 1e-10 from u = 0, best of 3 after one."""
+    import numpy as np
+    import torch
+
+    from paper_2403_08063_amd import GalerkinMultigrid, Multigrid, inputs
+
+    out = {}
+    for n, levels, seed in sizes:
+        k = torch.from_numpy(inputs.lognormal_k(3, n, seed=seed)).to(dev)
+        f = torch.from_numpy(inputs.constant_interior(3, n)).to(dev)
+        rec = {}
+        for name in ("galerkin", "rediscretised"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "galerkin":
+                mg = GalerkinMultigrid(k, levels)
+            else:
+                mg = Multigrid(3, n, levels, variable=True, device=dev)
+                mg.set_coefficients(k)
+            torch.cuda.synchronize()
+            t_setup = (time.perf_counter() - t0) * 1e3
+            ms = []
+            for rep in range(4):
+                u = torch.zeros_like(f)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u, info = mg.solve(f, u, tol=1e-10)
+                torch.cuda.synchronize()
+                if rep:
+                    ms.append((time.perf_counter() - t0) * 1e3)
+            rec[name] = {"setup_ms": round(t_setup, 2), "cycles": info.cycles,
+                         "relres": info.relres, "solve_ms": round(float(np.min(ms)), 2)}
+            if name == "galerkin":
+                ug = u.clone()
+            else:
+                rec["solution_rel_diff"] = float((ug - u).abs().max() / u.abs().max())
+            mg.close()
+            del mg, u
+        out[str(n)] = rec
+        print(f"bench: galerkin n={n}: {rec['galerkin']['cycles']} cycles {rec['galerkin']['solve_ms']} ms "
+              f"(setup {rec['galerkin']['setup_ms']} ms); rediscretised {rec['rediscretised']['cycles']} cycles "
+              f"{rec['rediscretised']['solve_ms']} ms", file=sys.stderr, flush=True)
+        del k, f, ug
+        torch.cuda.empty_cache()
+    return {"workload": "3D -div(k grad u) = 1, k = exp(GRF, corr 0.1, sigma 1), zero Dirichlet data, "
+                        "V(2,2), FP64 to 1e-10 relative residual; Galerkin R A P coarse operators "
+                        "(27-point, 8-colour Gauss-Seidel) vs rediscretised (7-point, geometric "
+                        "coefficient coarsening)", "sizes": out}
 
 
 def fv_benchmark(dev, copy_gbs: float, N: int = 512, cycles: int = 100):
@@ -451,6 +507,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fv", action="store_true")
     ap.add_argument("--no-blocks", action="store_true")
+    ap.add_argument("--no-galerkin", action="store_true")
+    ap.add_argument("--galerkin-only", action="store_true",
+                    help="run only the Galerkin-coarsening leg, print its record")
     ap.add_argument("--blocks-only", action="store_true",
                     help="run only the refined-block leg, print its record")
     ap.add_argument("--table1-max", type=int, default=128, choices=(64, 128, 256),
@@ -490,6 +549,11 @@ def main():
             rv.vcycle(fv, uv)
         torch.cuda.synchronize()
         print(f"bench: 6 block V-cycles at B={Bv} done", flush=True)
+        return
+    if args.galerkin_only:
+        import torch
+
+        print(json.dumps(galerkin_benchmark(torch.device("cuda:0"))), flush=True)
         return
     if args.blocks_only:
         import torch
@@ -682,6 +746,9 @@ def main():
         rec["fv_benchmark"] = fv_benchmark(dev, copy_gbs)
         print(f"bench: fv jacobi {rec['fv_benchmark']['jacobi_glups']} GLUP/s, V(3,3) "
               f"{rec['fv_benchmark']['vcycle_ms']} ms", file=sys.stderr, flush=True)
+    if not args.no_galerkin:
+        print("bench: Galerkin coarsening (lognormal k)", file=sys.stderr, flush=True)
+        rec["galerkin"] = galerkin_benchmark(dev)
     if not args.no_blocks:
         print("bench: refined block layout (Sect. 3/5)", file=sys.stderr, flush=True)
         rec["refined_blocks"] = refined_benchmark(dev, table_sizes=table_sizes)

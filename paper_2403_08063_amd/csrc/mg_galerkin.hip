@@ -60,28 +60,35 @@ __global__ void __launch_bounds__(kGalThreads)
   u[i] = (f[i] - offdiag(S, cnt, u, n, z, y, x, i)) / S[kCentre * cnt + i];
 }
 
-// fc = FW(f - A u) at coarse interior nodes (nf: fine nodes per side; f == nullptr reads 0)
+// r = f - A u at interior nodes (f == nullptr reads 0); the boundary of r is not written
 __global__ void __launch_bounds__(kGalThreads)
-    k_gal_restrict(int nf, const double* __restrict__ S, const double* __restrict__ f,
-                   const double* __restrict__ u, double* __restrict__ fc)
+    k_gal_residual(int n, const double* __restrict__ S, const double* __restrict__ f,
+                   const double* __restrict__ u, double* __restrict__ r)
+{
+  const int m = n - 2;
+  const int t = blockIdx.x * kGalThreads + threadIdx.x;
+  if (t >= m * m * m) return;
+  const int x = 1 + t % m, y = 1 + (t / m) % m, z = 1 + t / (m * m);
+  const size_t cnt = (size_t)n * n * n;
+  const size_t i = gidx(n, z, y, x);
+  const double au = S[kCentre * cnt + i] * u[i] + offdiag(S, cnt, u, n, z, y, x, i);
+  r[i] = (f ? f[i] : 0.0) - au;
+}
+
+// fc = full weighting of r at coarse interior nodes (nf: fine nodes per side)
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_fw(int nf, const double* __restrict__ r, double* __restrict__ fc)
 {
   const int nc = (nf - 1) / 2 + 1, m = nc - 2;
   const int t = blockIdx.x * kGalThreads + threadIdx.x;
   if (t >= m * m * m) return;
   const int X = 1 + t % m, Y = 1 + (t / m) % m, Z = 1 + t / (m * m);
-  const size_t cnt = (size_t)nf * nf * nf;
   double s = 0.0;
-#pragma unroll 1
   for (int oz = -1; oz <= 1; ++oz)
-#pragma unroll 1
     for (int oy = -1; oy <= 1; ++oy)
       for (int ox = -1; ox <= 1; ++ox) {
-        const int z = 2 * Z + oz, y = 2 * Y + oy, x = 2 * X + ox;  // always interior
-        const size_t i = gidx(nf, z, y, x);
-        const double au = S[kCentre * cnt + i] * u[i] + offdiag(S, cnt, u, nf, z, y, x, i);
-        const double r = (f ? f[i] : 0.0) - au;
         const double w = (oz ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (ox ? 0.25 : 0.5);
-        s += w * r;
+        s += w * r[gidx(nf, 2 * Z + oz, 2 * Y + oy, 2 * X + ox)];
       }
   fc[gidx(nc, Z, Y, X)] = s;
 }
@@ -130,6 +137,7 @@ struct GalLevel {
   size_t cnt = 0;
   double* u = nullptr;  // correction (levels >= 1)
   double* f = nullptr;  // right-hand side (levels >= 1)
+  double* r = nullptr;  // residual (levels >= 1)
   double* S = nullptr;  // 27 stencil arrays (levels >= 1)
 };
 
@@ -138,7 +146,7 @@ struct mggal_ctx {
   hipStream_t s = nullptr;
   double h = 0;
   double* k = nullptr;      // copy of the coefficient
-  double* probe = nullptr;  // level-0 probe vector
+  double* probe = nullptr;  // level-0 probe vector; the sweeps' second buffer after setup
   double* zero = nullptr;   // level-0 zero right-hand side (probing)
   double* partial = nullptr;
   double* scal = nullptr;
@@ -198,7 +206,7 @@ void gal_layout(const mggal_grid* g, GalCarver& cv, mggal_ctx* c)
   double* k = cv.take<double>(cnt0);
   double* probe = cv.take<double>(cnt0);
   double* zero = cv.take<double>(cnt0);
-  double* partial = cv.take<double>(mgk::kNormBlocks);
+  double* partial = cv.take<double>(mgk::kStreamPartials);
   double* scal = cv.take<double>(8);
   std::vector<GalLevel> lv;
   int n = g->n;
@@ -209,6 +217,7 @@ void gal_layout(const mggal_grid* g, GalCarver& cv, mggal_ctx* c)
     if (l > 0) {
       L.u = cv.take<double>(L.cnt);
       L.f = cv.take<double>(L.cnt);
+      L.r = cv.take<double>(L.cnt);
       L.S = cv.take<double>(27 * L.cnt);
     }
     lv.push_back(L);
@@ -224,9 +233,26 @@ void gal_layout(const mggal_grid* g, GalCarver& cv, mggal_ctx* c)
   }
 }
 
+// level 0 on a large grid: the streaming kernels of the rediscretised path
+bool fine_tiled(const mggal_ctx* c) { return mgk::rbgs_tiled_supported(3, c->g.n); }
+
 void smooth(mggal_ctx* c, int l, const double* f, double* u, int sweeps)
 {
   const GalLevel& L = c->lv[l];
+  if (l == 0 && fine_tiled(c)) {
+    // one red-black sweep per out-of-place pass, alternating with the second buffer (same
+    // boundary values)
+    mgk::copy_boundary(c->s, 3, L.n, u, c->probe);
+    double *cur = u, *oth = c->probe;
+    for (int s = 0; s < sweeps; ++s) {
+      mgk::rbgs_tiled<double>(c->s, L.n, c->h, c->k, f, cur, oth, 1, false);
+      double* x = cur;
+      cur = oth;
+      oth = x;
+    }
+    if (cur != u) mgk::copy<double>(c->s, L.cnt, cur, u);
+    return;
+  }
   for (int s = 0; s < sweeps; ++s) {
     if (l == 0) {
       mgk::rbgs_colour<double>(c->s, 3, L.n, c->h, c->k, f, u, 0);
@@ -244,10 +270,12 @@ void restrict_to(mggal_ctx* c, int l, const double* f, const double* u, double* 
 {
   const GalLevel& L = c->lv[l];
   if (l == 0) {
-    mgk::restrict_residual<double>(c->s, 3, L.n, c->h, c->k, f ? f : c->zero, u, fc);
+    if (fine_tiled(c)) mgk::restrict_residual_tiled<double>(c->s, L.n, c->h, c->k, f ? f : c->zero, u, fc);
+    else mgk::restrict_residual<double>(c->s, 3, L.n, c->h, c->k, f ? f : c->zero, u, fc);
   } else {
-    const size_t m = (size_t)c->lv[l + 1].n - 2;
-    k_gal_restrict<<<blocks_for(m * m * m), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, fc);
+    const size_t mf = (size_t)L.n - 2, mc = (size_t)c->lv[l + 1].n - 2;
+    k_gal_residual<<<blocks_for(mf * mf * mf), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, L.r);
+    k_gal_fw<<<blocks_for(mc * mc * mc), kGalThreads, 0, c->s>>>(L.n, L.r, fc);
   }
 }
 
@@ -288,7 +316,8 @@ void build_level(mggal_ctx* c, int l)
 
 mg_status read_norm2(mggal_ctx* c, const double* f, const double* u, int mode, double* out)
 {
-  mgk::resid_norm2(c->s, 3, c->g.n, c->h, c->k, f, u, mode, c->partial, c->scal);
+  if (fine_tiled(c)) mgk::resid_norm2_tiled(c->s, c->g.n, c->h, c->k, f, u, mode, c->partial, c->scal);
+  else mgk::resid_norm2(c->s, 3, c->g.n, c->h, c->k, f, u, mode, c->partial, c->scal);
   if (mg_status st = gal_hip(c, hipGetLastError(), "norm")) return st;
   if (mg_status st = gal_hip(c, hipMemcpyAsync(out, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->s),
                              "reading the norm"))
@@ -333,6 +362,7 @@ mg_status mggal_setup(const mggal_grid* grid, const double* k, void* workspace, 
   for (size_t l = 1; l < c->lv.size(); ++l) {  // zero boundaries of every coarse array
     mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, c->lv[l].u);
     mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, c->lv[l].f);
+    mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, c->lv[l].r);
   }
   for (size_t l = 0; l + 1 < c->lv.size(); ++l) build_level(c, (int)l);
   mg_status st = gal_hip(c, hipGetLastError(), "building the Galerkin hierarchy");
