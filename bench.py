@@ -580,7 +580,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
-              "multi-GPU path; see the sharding design in DESIGN.md", file=sys.stderr)
+              "multi-GPU path (it would split the grid into z-slabs with a halo exchange per "
+              "half-sweep)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
