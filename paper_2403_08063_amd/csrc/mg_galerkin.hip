@@ -3,7 +3,9 @@
 // Gauss-Seidel with face coefficients, residual + full weighting, trilinear prolongation,
 // norms); the coarse levels hold 27-point stencils built on the GPU by probing R A P with
 // combs of coarse nodes, and run the kernels below: eight-colour Gauss-Seidel, residual with
-// full weighting, and the exact solve of the one-node coarsest level.
+// full weighting, and the exact solve of the one-node coarsest level.  A coarse level stores
+// its stencil colour-major: for each of the eight parity colours, 27 arrays over that colour's
+// nodes in C order, so that a colour pass of the smoother reads its coefficients contiguously.
 #include "../../include/mg_galerkin.h"
 #include "mg_kernels.h"
 
@@ -29,17 +31,34 @@ __device__ __forceinline__ size_t gidx(int n, int z, int y, int x)
   return ((size_t)z * n + y) * (size_t)n + x;
 }
 
+// Colour-major stencil storage of a level with n nodes per side: half = (n-1)/2 slots per axis
+// and colour; interior index v of parity p sits in slot (v - 2 + p) / 2; the coefficient of
+// offset o at a node of colour c and slot t is S[(c * 27 + o) * half^3 + t].
+__device__ __forceinline__ int colour_of(int z, int y, int x) { return 4 * (z & 1) + 2 * (y & 1) + (x & 1); }
+
+__device__ __forceinline__ size_t slot_of(int half, int z, int y, int x)
+{
+  const int jz = (z - 2 + (z & 1)) / 2, jy = (y - 2 + (y & 1)) / 2, jx = (x - 2 + (x & 1)) / 2;
+  return ((size_t)jz * half + jy) * half + jx;
+}
+
+// first coefficient (offset 0) of interior node (z, y, x); offset o at + o * half^3
+__device__ __forceinline__ const double* node_coeffs(const double* S, int half, int z, int y, int x)
+{
+  const size_t h3 = (size_t)half * half * half;
+  return S + (size_t)colour_of(z, y, x) * 27 * h3 + slot_of(half, z, y, x);
+}
+
 // (A u)_i - a_ii u_i: the off-diagonal part of the 27-point stencil at interior node i
-__device__ __forceinline__ double offdiag(const double* __restrict__ S, size_t cnt,
-                                          const double* __restrict__ u, int n, int z, int y,
-                                          int x, size_t i)
+__device__ __forceinline__ double offdiag(const double* __restrict__ Sn, size_t h3,
+                                          const double* __restrict__ u, int n, int z, int y, int x)
 {
   double s = 0.0;
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
     if (o == kCentre) continue;
     const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
-    s += S[o * cnt + i] * u[gidx(n, z + dz, y + dy, x + dx)];
+    s += Sn[o * h3] * u[gidx(n, z + dz, y + dy, x + dx)];
   }
   return s;
 }
@@ -55,9 +74,10 @@ __global__ void __launch_bounds__(kGalThreads)
   // interior index with parity p: 2 j + 2 - p  (p = 1: 1, 3, ..; p = 0: 2, 4, ..)
   const int x = 2 * (t % half) + 2 - px, y = 2 * ((t / half) % half) + 2 - py, z = 2 * (t / (half * half)) + 2 - pz;
   if (x > n - 2 || y > n - 2 || z > n - 2) return;
-  const size_t cnt = (size_t)n * n * n;
+  const size_t h3 = (size_t)half * half * half;
+  const double* Sn = S + (size_t)c * 27 * h3 + t;
   const size_t i = gidx(n, z, y, x);
-  u[i] = (f[i] - offdiag(S, cnt, u, n, z, y, x, i)) / S[kCentre * cnt + i];
+  u[i] = (f[i] - offdiag(Sn, h3, u, n, z, y, x)) / Sn[kCentre * h3];
 }
 
 // r = f - A u at interior nodes (f == nullptr reads 0); the boundary of r is not written
@@ -69,9 +89,11 @@ __global__ void __launch_bounds__(kGalThreads)
   const int t = blockIdx.x * kGalThreads + threadIdx.x;
   if (t >= m * m * m) return;
   const int x = 1 + t % m, y = 1 + (t / m) % m, z = 1 + t / (m * m);
-  const size_t cnt = (size_t)n * n * n;
+  const int half = (n - 1) / 2;
+  const size_t h3 = (size_t)half * half * half;
+  const double* Sn = node_coeffs(S, half, z, y, x);
   const size_t i = gidx(n, z, y, x);
-  const double au = S[kCentre * cnt + i] * u[i] + offdiag(S, cnt, u, n, z, y, x, i);
+  const double au = Sn[kCentre * h3] * u[i] + offdiag(Sn, h3, u, n, z, y, x);
   r[i] = (f ? f[i] : 0.0) - au;
 }
 
@@ -116,16 +138,32 @@ __global__ void __launch_bounds__(kGalThreads)
   const int X = 1 + t % m, Y = 1 + (t / m) % m, Z = 1 + t / (m * m);
   auto off = [](int c, int I) { const int r = ((c - I) % 3 + 3) % 3; return r == 2 ? -1 : r; };
   const int o = 9 * (off(cz, Z) + 1) + 3 * (off(cy, Y) + 1) + (off(cx, X) + 1);
-  const size_t i = gidx(nc, Z, Y, X);
-  S[o * (size_t)nc * nc * nc + i] = -fc[i];
+  const int half = (nc - 1) / 2;
+  const size_t h3 = (size_t)half * half * half;
+  const_cast<double*>(node_coeffs(S, half, Z, Y, X))[o * h3] = -fc[gidx(nc, Z, Y, X)];
 }
 
-// the coarsest level (3^3 nodes): its one interior node
+// the coarsest level (3^3 nodes): its one interior node (colour 7, slot 0 of one)
 __global__ void k_gal_coarsest(const double* __restrict__ S, const double* __restrict__ f,
                                double* __restrict__ u)
 {
   const size_t i = gidx(3, 1, 1, 1);
-  u[i] = f[i] / S[kCentre * 27 + i];
+  u[i] = f[i] / node_coeffs(S, 1, 1, 1, 1)[kCentre];
+}
+
+// out[o][i] = the stencil in natural layout (27 arrays of n^3 values, 0 off the interior)
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_export(int n, const double* __restrict__ S, double* __restrict__ out)
+{
+  const size_t t = (size_t)blockIdx.x * kGalThreads + threadIdx.x;
+  const size_t cnt = (size_t)n * n * n;
+  if (t >= cnt) return;
+  const int x = (int)(t % n), y = (int)((t / n) % n), z = (int)(t / ((size_t)n * n));
+  const bool in = x > 0 && y > 0 && z > 0 && x < n - 1 && y < n - 1 && z < n - 1;
+  const int half = (n - 1) / 2;
+  const size_t h3 = (size_t)half * half * half;
+  const double* Sn = in ? node_coeffs(S, half, z, y, x) : nullptr;
+  for (int o = 0; o < 27; ++o) out[o * cnt + t] = in ? Sn[o * h3] : 0.0;
 }
 
 unsigned blocks_for(size_t count) { return (unsigned)((count + kGalThreads - 1) / kGalThreads); }
@@ -135,10 +173,11 @@ unsigned blocks_for(size_t count) { return (unsigned)((count + kGalThreads - 1) 
 struct GalLevel {
   int n = 0;
   size_t cnt = 0;
+  size_t scnt = 0;      // doubles of the colour-major stencil: 8 colours x 27 x ((n-1)/2)^3
   double* u = nullptr;  // correction (levels >= 1)
   double* f = nullptr;  // right-hand side (levels >= 1)
   double* r = nullptr;  // residual (levels >= 1)
-  double* S = nullptr;  // 27 stencil arrays (levels >= 1)
+  double* S = nullptr;  // colour-major stencil (levels >= 1)
 };
 
 struct mggal_ctx {
@@ -214,11 +253,13 @@ void gal_layout(const mggal_grid* g, GalCarver& cv, mggal_ctx* c)
     GalLevel L;
     L.n = n;
     L.cnt = (size_t)n * n * n;
+    const size_t half = (size_t)(n - 1) / 2;
+    L.scnt = 8 * 27 * half * half * half;
     if (l > 0) {
       L.u = cv.take<double>(L.cnt);
       L.f = cv.take<double>(L.cnt);
       L.r = cv.take<double>(L.cnt);
-      L.S = cv.take<double>(27 * L.cnt);
+      L.S = cv.take<double>(L.scnt);
     }
     lv.push_back(L);
     n = (n - 1) / 2 + 1;
@@ -301,7 +342,7 @@ void build_level(mggal_ctx* c, int l)
   GalLevel& F = c->lv[l];
   GalLevel& C = c->lv[l + 1];
   double* w = l == 0 ? c->probe : F.u;  // fine probe vector (zero boundary)
-  mgk::fill<double>(c->s, 27 * C.cnt, 0.0, C.S);
+  mgk::fill<double>(c->s, C.scnt, 0.0, C.S);
   const size_t m = (size_t)C.n - 2;
   for (int cz = 0; cz < 3; ++cz)
     for (int cy = 0; cy < 3; ++cy)
@@ -385,8 +426,9 @@ mg_status mggal_stencil(mggal_ctx* c, int level, double* out)
   if (!c) return gal_fail(nullptr, MG_EINVAL, "context is NULL");
   if (level < 1 || level >= (int)c->lv.size()) return gal_fail(c, MG_EINVAL, "level %d has no stencil", level);
   if (!out) return gal_fail(c, MG_EINVAL, "out is NULL");
-  mgk::copy<double>(c->s, 27 * c->lv[level].cnt, c->lv[level].S, out);
-  return gal_hip(c, hipGetLastError(), "copying the stencil");
+  const GalLevel& L = c->lv[level];
+  k_gal_export<<<blocks_for(L.cnt), kGalThreads, 0, c->s>>>(L.n, L.S, out);
+  return gal_hip(c, hipGetLastError(), "exporting the stencil");
 }
 
 mg_status mggal_vcycle(mggal_ctx* c, const double* f, double* u)

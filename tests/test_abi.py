@@ -186,14 +186,14 @@ def test_gal_invalid_grids_need_no_workspace(kw):
 
 def test_gal_workspace_size():
     """Coefficient copy, probe and zero vectors on the fine level; correction, right-hand side,
-    residual and 27 stencil arrays on every coarser level (256-byte aligned), plus partial
-    sums."""
+    residual and the colour-major stencil (8 colours x 27 x ((n_l - 1)/2)^3) on every coarser
+    level (256-byte aligned), plus partial sums."""
     n, levels = 33, 5
     al = lambda b: -(-b // 256) * 256  # noqa: E731
     want = 3 * al(n ** 3 * 8)
     nl = n
     for _ in range(1, levels):
         nl = (nl - 1) // 2 + 1
-        want += 3 * al(nl ** 3 * 8) + al(27 * nl ** 3 * 8)
+        want += 3 * al(nl ** 3 * 8) + al(8 * 27 * ((nl - 1) // 2) ** 3 * 8)
     got = gal_bytes(n=n, levels=levels)
     assert want <= got <= want + 16384 * 8 + 4 * 256
