@@ -197,3 +197,38 @@ def test_gal_workspace_size():
         want += 3 * al(nl ** 3 * 8) + al(8 * 27 * ((nl - 1) // 2) ** 3 * 8)
     got = gal_bytes(n=n, levels=levels)
     assert want <= got <= want + 16384 * 8 + 4 * 256
+
+
+def test_block_and_galerkin_entry_points_reject_bad_arguments_before_gpu_work():
+    """Every new entry point validates its arguments before any HIP call: NULL contexts and
+    pointers, invalid descriptions, a workspace too small or misaligned."""
+    lib = _lib.lib()
+    out = ctypes.c_void_p(1)
+    # refined blocks
+    g = MgBlkGrid(16, 2, 0.8, 4, 3, 3, 256, 35)  # 16 has only 3 levels of even sizes >= 4
+    assert lib.mgblk_setup(ctypes.byref(g), ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(out)) == MG_EINVAL
+    assert out.value is None and "levels" in lib.mgblk_last_error(None).decode()
+    g = MgBlkGrid(16, 2, 0.8, 0, 3, 3, 256, 35)
+    assert lib.mgblk_setup(ctypes.byref(g), ctypes.c_void_p(256), 16, None, ctypes.byref(out)) == 2
+    assert lib.mgblk_setup(ctypes.byref(g), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(out)) == MG_EINVAL
+    assert lib.mgblk_levels(None) == 0
+    for call in (lambda: lib.mgblk_vcycle(None, None, None),
+                 lambda: lib.mgblk_mg_solve(None, None, None, 1e-10, None, None),
+                 lambda: lib.mgblk_smooth(None, 0, None, None, 1),
+                 lambda: lib.mgblk_restrict_residual(None, 0, None, None, None),
+                 lambda: lib.mgblk_prolong_correct(None, 0, None, None)):
+        assert call() == MG_EINVAL
+    # Galerkin coarsening
+    gg = MgGalGrid(33, 4, 2, 2, 100)  # 33 needs 5 levels to reach 3 nodes
+    assert lib.mggal_setup(ctypes.byref(gg), ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 40, None,
+                           ctypes.byref(out)) == MG_EINVAL
+    assert out.value is None and "levels" in lib.mggal_last_error(None).decode()
+    gg = MgGalGrid(33, 5, 2, 2, 100)
+    assert lib.mggal_setup(ctypes.byref(gg), None, ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(out)) == MG_EINVAL
+    assert "k is NULL" in lib.mggal_last_error(None).decode()
+    assert lib.mggal_setup(ctypes.byref(gg), ctypes.c_void_p(256), ctypes.c_void_p(256), 16, None,
+                           ctypes.byref(out)) == 2
+    for call in (lambda: lib.mggal_vcycle(None, None, None),
+                 lambda: lib.mggal_solve(None, None, None, 1e-10, None, None),
+                 lambda: lib.mggal_stencil(None, 1, None)):
+        assert call() == MG_EINVAL
