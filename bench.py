@@ -494,7 +494,46 @@ def cpu_baseline(f_np, levels, fp64_cycles):
                   f"the FP64 cycle count ({fp64_cycles})",
         "value_1_thread": round(t1 * fp64_cycles * 1e3, 1),
         "cpu_model": _cpu_model(),
+        "next_rows": next_rows_baseline(threads),
     }
+
+
+def next_rows_baseline(threads):
+    """The oracles of the components beyond the hot path, each timed once on a bounded sample
+    beside the GPU leg that measures the same operation: the FV V(3,3)-cycle (C oracle, all
+    threads), the refined-layout V(3,3)-cycle (numpy oracle) and the Galerkin solve (scipy
+    oracle), with the time per million cells for comparison with the GPU figures."""
+    import numpy as np
+
+    import oracle
+    from oracle import blocks as oblocks
+    from oracle import galerkin as ogal
+    from paper_2403_08063_amd import inputs
+
+    out = {}
+    N = 256
+    u, _ = inputs.fv_harmonic(N)
+    t0 = time.perf_counter()
+    oracle.fv_vcycle(np.zeros_like(u), u, N.bit_length() - 2)
+    t = time.perf_counter() - t0
+    out["fv_vcycle"] = {"ms": round(t * 1e3, 1), "ms_per_mcell": round(t * 1e3 / (N ** 3 / 1e6), 2),
+                        "sample": f"one V(3,3) cycle, {N}^3 cells, C oracle at {threads} threads"}
+    B = 16
+    u0, _ = inputs.block_harmonic(B)
+    t0 = time.perf_counter()
+    oblocks.vcycle(u0.reshape(-1).copy(), np.zeros(u0.size), oblocks.mg_block_sizes(B), 2)
+    t = time.perf_counter() - t0
+    out["blocks_vcycle"] = {"ms": round(t * 1e3, 1), "ms_per_mcell": round(t * 1e3 / (120 * B ** 3 / 1e6), 2),
+                            "sample": f"one V(3,3) cycle, 120 blocks of {B}^3 cells, quadratic C2F, numpy oracle"}
+    n = 65
+    k, f = inputs.lognormal_k(3, n, seed=4), inputs.constant_interior(3, n)
+    t0 = time.perf_counter()
+    _, cycles, _ = ogal.solve(k, f, 6)
+    t = time.perf_counter() - t0
+    out["galerkin_solve"] = {"ms": round(t * 1e3, 1), "cycles": cycles,
+                             "ms_per_mcell": round(t * 1e3 / (n ** 3 / 1e6), 2),
+                             "sample": f"setup + FP64 solve to 1e-10, {n}^3 nodes, lognormal k, scipy oracle"}
+    return out
 
 
 def main():
