@@ -26,7 +26,8 @@ class GalerkinMultigrid:
         if k.device.type != "cuda":
             raise ValueError("GalerkinMultigrid runs on a GPU device")
         self.n = int(k.shape[0])
-        self.levels = int(levels) if levels is not None else max(2, (self.n - 1).bit_length())
+        # by default down to 3 nodes per side: n = 2^m + 1 has m levels
+        self.levels = int(levels) if levels is not None else max(2, (self.n - 1).bit_length() - 1)
         self.device = k.device
         self.grid = MgGalGrid(self.n, self.levels, int(nu1), int(nu2), int(max_cycles))
         L = lib()

@@ -107,3 +107,10 @@ def test_workload_size_fewer_cycles_than_rediscretisation():
     d = (u - u2).abs().max().item() / u2.abs().max().item()
     assert d <= 1e-8, d
     mg.close()
+
+
+def test_default_levels_reach_three_nodes():
+    for n, levels in ((5, 2), (17, 4), (33, 5)):
+        mg = GalerkinMultigrid(to_gpu(inputs.lognormal_k(3, n, seed=4)))
+        assert mg.levels == levels and mg.level_n(levels - 1) == 3
+        mg.close()
