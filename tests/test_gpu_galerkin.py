@@ -114,3 +114,25 @@ def test_default_levels_reach_three_nodes():
         mg = GalerkinMultigrid(to_gpu(inputs.lognormal_k(3, n, seed=4)))
         assert mg.levels == levels and mg.level_n(levels - 1) == 3
         mg.close()
+
+
+def test_differentiable_solve_with_galerkin_coarsening():
+    """solve(..., coarsening="galerkin") solves the same discrete system as the rediscretised
+    hierarchy: the solution and both gradients (dL/dk, dL/df) agree to the solve tolerance."""
+    from paper_2403_08063_amd import solve
+
+    n = 33
+    say("galerkin autograd n=33")
+    rng = np.random.default_rng(21)
+    w = torch.from_numpy(rng.uniform(-1, 1, (n, n, n))).to(DEV)
+    out = {}
+    for coarsening in ("rediscretise", "galerkin"):
+        k = to_gpu(inputs.lognormal_k(3, n, seed=4)).requires_grad_(True)
+        f = to_gpu(inputs.constant_interior(3, n)).requires_grad_(True)
+        u = solve(k, f, tol=1e-12, coarsening=coarsening)
+        (u * w).sum().backward()
+        out[coarsening] = (u.detach(), k.grad, f.grad)
+    for a, b in zip(out["rediscretise"], out["galerkin"]):
+        assert (a - b).abs().max().item() <= 1e-8 * b.abs().max().item()
+    with pytest.raises(ValueError):
+        solve(to_gpu(inputs.lognormal_k(3, n, seed=4)), to_gpu(inputs.constant_interior(3, n)), coarsening="x")
