@@ -136,3 +136,29 @@ def test_differentiable_solve_with_galerkin_coarsening():
         assert (a - b).abs().max().item() <= 1e-8 * b.abs().max().item()
     with pytest.raises(ValueError):
         solve(to_gpu(inputs.lognormal_k(3, n, seed=4)), to_gpu(inputs.constant_interior(3, n)), coarsening="x")
+
+
+def test_nonzero_dirichlet_data_matches_rediscretised_solution():
+    """u's boundary values are Dirichlet data for the Galerkin solver as for Multigrid: both
+    solve the same discrete system, so the solutions agree to the tolerance's order."""
+    n, levels = 33, 5
+    say("galerkin nonzero Dirichlet data n=33")
+    k = to_gpu(inputs.lognormal_k(3, n, seed=4))
+    f = to_gpu(inputs.uniform_interior(3, n, seed=12))
+    ub = np.zeros((n, n, n))
+    x = np.linspace(0.0, 1.0, n)
+    g = np.sin(np.pi * x)[None, None, :] + x[:, None, None] * x[None, :, None]
+    for sl in ((0,), (-1,)):
+        ub[sl[0], :, :] = g[sl[0], :, :]
+        ub[:, sl[0], :] = g[:, sl[0], :]
+        ub[:, :, sl[0]] = g[:, :, sl[0]]
+    u1 = to_gpu(ub)
+    mg = GalerkinMultigrid(k, levels)
+    u1, info = mg.solve(f, u1, tol=1e-12)
+    r = Multigrid(3, n, levels, variable=True)
+    r.set_coefficients(k)
+    u2, info2 = r.solve(f, to_gpu(ub), tol=1e-12)
+    assert info.converged and info2.converged
+    assert np.array_equal(u1.cpu().numpy()[0], ub[0]) and np.array_equal(u1.cpu().numpy()[:, :, -1], ub[:, :, -1])
+    assert (u1 - u2).abs().max().item() <= 1e-9 * u2.abs().max().item()
+    mg.close()
