@@ -106,6 +106,56 @@ def pmc_sample(n: int):
     print("pmc sample done", file=sys.stderr)
 
 
+def pmc_fv_sample(N: int = 512):
+    """Counter-run workload for the paper's FV sweep: the calibration copy, then 10 damped
+    Jacobi sweeps on the 512^3-cell level (the exact-partition pass)."""
+    import torch
+
+    from paper_2403_08063_amd import FVMultigrid, inputs
+
+    dev = torch.device("cuda:0")
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    u0, _ = inputs.fv_harmonic(N)
+    mg = FVMultigrid(N, device=dev)
+    u = torch.from_numpy(u0).to(dev)
+    mg.jacobi(0, torch.zeros_like(u), u, 10)
+    torch.cuda.synchronize()
+    print("pmc fv sample done", file=sys.stderr)
+
+
+def summarize_pmc_fv(fetch_dir: str, write_dir: str, N: int = 512):
+    """Per-launch HBM bytes of the FV Jacobi pass from the two counter runs of
+    pmc_fv_sample, calibrated as summarize_pmc does; printed, not stored."""
+    import csv
+    import glob
+
+    out = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        copy = [v for name, v in rows if "copy" in name.lower() and "fill" not in name.lower()]
+        sweep = [v for name, v in rows if "k_pass<false, 4," in name]
+        if not copy or not sweep:
+            raise SystemExit(f"{counter}: no calibration copy or FV sweep dispatch in {d}")
+        factor = (CALIB_BYTES / 1024.0) / copy[0]
+        out[key] = {"counter_kib_per_launch": sum(sweep) / len(sweep), "calibration_kib": copy[0],
+                    "scale": factor, "bytes_per_launch": sum(sweep) / len(sweep) * 1024.0 * factor,
+                    "launches": len(sweep)}
+    total = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    alg = 24 * N ** 3
+    print(json.dumps({"kernel": "k_pass<false, 4, ..> (FV damped Jacobi sweep)", "N": N,
+                      "fetch": out["fetch"], "write": out["write"], "bytes_per_launch": total,
+                      "algorithmic_bytes_per_launch": alg, "traffic_over_algorithmic": total / alg},
+                     indent=1))
+
+
 def summarize_pmc(fetch_dir: str, write_dir: str, n: int):
     """Per-launch HBM bytes of the fused FP64 smoother from the two counter runs, each
     counter scaled so that the calibration copy reads exactly its known size."""
@@ -560,6 +610,9 @@ def main():
                     help="run only the paper-benchmark (cell-centred FV) leg, print its record")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--pmc-fv-sample", action="store_true",
+                    help="counter-run workload: calibration copy + 10 FV Jacobi sweeps at 512^3")
+    ap.add_argument("--summarize-pmc-fv", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", nargs="+", metavar=("TRACE_DIR", "BENCH_LOG"))
     ap.add_argument("--by-grid", action="store_true",
                     help="with --summarize-trace: add a table per kernel and launch grid")
@@ -572,6 +625,12 @@ def main():
         return
     if args.pmc_sample:
         pmc_sample(args.n)
+        return
+    if args.pmc_fv_sample:
+        pmc_fv_sample()
+        return
+    if args.summarize_pmc_fv:
+        summarize_pmc_fv(*args.summarize_pmc_fv)
         return
     table_sizes = tuple(b for b in (16, 32, 64, 128, 256) if b <= args.table1_max)
     if args.blocks_vcycle_sample:
