@@ -21,6 +21,9 @@ Also reported:
     time of a V(3,3) cycle over 100 cycles with 256 coarsest iterations (Sect. 6), and the
     L2 error of the harmonic problem (Eq. 1-2) at 256^3 and 512^3 cells with its
     grid-convergence ratio kappa (Eq. 3).  --no-fv skips it;
+  - the differentiable variable-coefficient solve ("gradient") on workloads 4 (257^3, FP64)
+    and 5 (513^3, FP32-refined): forward solve, adjoint solve, the fused gradient pass (and its
+    bandwidth at 32 B per node) and one torch.autograd step.  --no-gradient skips it;
   - Galerkin coarse operators ("galerkin") against the rediscretised hierarchy on the
     lognormal-coefficient workloads at 257^3 and 513^3: setup, cycles and time of an FP64
     solve to 1e-10.  --no-galerkin skips it;
@@ -259,6 +262,72 @@ def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24, by_gri
         for (k, g), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
             lines.append(f"| `{k}` | {g} | {n} | {t / 1e3:.2f} | {t / n:.1f} |")
     print("\n".join(head + [""] + lines))
+
+
+def gradient_benchmark(dev, workloads=((4, "f64"), (5, "f32_ir"))):
+    """The differentiable variable-coefficient solve on its workloads (k = exp(GRF), f = 1,
+    L = 0.5 ||u - u_obs||^2 with u_obs the solution for the perturbed coefficient k_obs):
+    forward solve, adjoint solve and the fused gradient pass timed one by one (best of 3
+    after one), and one whole torch.autograd step (forward, loss, backward with the forward
+    recomputed) through solve()."""
+    import numpy as np
+    import torch
+
+    from paper_2403_08063_amd import Multigrid, inputs, solve
+
+    out = {}
+    for idx, prec in workloads:
+        w = inputs.config(idx)
+        n, levels = w["n"], w["levels"]
+        k = torch.from_numpy(w["k"]).to(dev)
+        kobs = torch.from_numpy(w["k_obs"]).to(dev)
+        f = torch.from_numpy(w["f"]).to(dev)
+        mg = Multigrid(3, n, levels, precision=prec, variable=True, device=dev)
+        mg.set_coefficients(kobs)
+        uobs, _ = mg.solve(f, mg.zeros(), tol=1e-10)
+        mg.set_coefficients(k)
+
+        def best(fn, reps=3):
+            fn()
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return float(np.min(ts)), r
+
+        t_fwd, (u, info) = best(lambda: mg.solve(f, mg.zeros(), tol=1e-10))
+        g = (u - uobs).contiguous()
+        t_adj, (lam, info_a) = best(lambda: mg.solve_adjoint(g, mg.zeros(), tol=1e-10))
+        t_grad, _ = best(lambda: mg.grad(u, lam), reps=5)
+
+        def step():
+            kk = k.clone().requires_grad_(True)
+            uu = solve(kk, f, mg=mg, tol=1e-10, precision=prec)
+            loss = 0.5 * ((uu - uobs) ** 2).sum()
+            loss.backward()
+            return kk.grad
+
+        t_step, _ = best(step)
+        out[str(idx)] = {
+            "n": n, "precision": prec,
+            "forward_ms": round(t_fwd, 2), "forward_cycles": info.cycles,
+            "adjoint_ms": round(t_adj, 2), "adjoint_cycles": info_a.cycles,
+            "grad_pass_ms": round(t_grad, 3),
+            "grad_pass_gbs": round(32 * n ** 3 / (t_grad * 1e-3) / 1e9, 1),
+            "autograd_step_ms": round(t_step, 1),
+        }
+        print(f"bench: gradient workload {idx} ({n}^3, {prec}): forward {t_fwd:.1f} ms "
+              f"({info.cycles} cycles), adjoint {t_adj:.1f} ms, gradient pass {t_grad:.3f} ms, "
+              f"autograd step {t_step:.1f} ms", file=sys.stderr, flush=True)
+        mg.close()
+        del k, kobs, f, uobs, u, g, lam
+        torch.cuda.empty_cache()
+    return {"workload": "3D -div(k grad u) = 1, k = exp(GRF, corr 0.1, sigma 1), zero Dirichlet data; "
+                        "L = 0.5 ||u - u_obs||^2; solves to 1e-10; gradient pass 32 B per node "
+                        "(read u, lambda; write dk, df)", "workloads": out}
 
 
 def galerkin_benchmark(dev, sizes=((257, 8, 4), (513, 9, 5))):
@@ -597,6 +666,9 @@ def main():
     ap.add_argument("--no-fv", action="store_true")
     ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--no-galerkin", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--gradient-only", action="store_true",
+                    help="run only the differentiable-solve leg, print its record")
     ap.add_argument("--galerkin-only", action="store_true",
                     help="run only the Galerkin-coarsening leg, print its record")
     ap.add_argument("--blocks-only", action="store_true",
@@ -647,6 +719,11 @@ def main():
             rv.vcycle(fv, uv)
         torch.cuda.synchronize()
         print(f"bench: 6 block V-cycles at B={Bv} done", flush=True)
+        return
+    if args.gradient_only:
+        import torch
+
+        print(json.dumps(gradient_benchmark(torch.device("cuda:0"))), flush=True)
         return
     if args.galerkin_only:
         import torch
@@ -845,6 +922,9 @@ def main():
         rec["fv_benchmark"] = fv_benchmark(dev, copy_gbs)
         print(f"bench: fv jacobi {rec['fv_benchmark']['jacobi_glups']} GLUP/s, V(3,3) "
               f"{rec['fv_benchmark']['vcycle_ms']} ms", file=sys.stderr, flush=True)
+    if not args.no_gradient:
+        print("bench: differentiable solve (lognormal k)", file=sys.stderr, flush=True)
+        rec["gradient"] = gradient_benchmark(dev)
     if not args.no_galerkin:
         print("bench: Galerkin coarsening (lognormal k)", file=sys.stderr, flush=True)
         rec["galerkin"] = galerkin_benchmark(dev)

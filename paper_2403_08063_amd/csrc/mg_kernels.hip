@@ -310,39 +310,45 @@ __global__ void __launch_bounds__(kBlock)
 // ------------------------------------------------------------------ adjoint gradient
 // dk_j = -1/(2h^2) sum_{axis neighbours m in the grid} (lam_j - lam_m)(u_j - u_m) with lam
 // read as 0 on boundary nodes; df_j = lam_j on interior nodes, 0 on the boundary.
+// One wave per grid row (kBlock / 64 rows per workgroup), stepping along x by 64: rows of
+// n = 2^m + 1 nodes leave one lane of the last step busy instead of most of a workgroup idle.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock)
     k_grad(const double* __restrict__ u, const double* __restrict__ lam, double* __restrict__ dk,
            double* __restrict__ df, int n, double c)
 {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  const int z = DIM == 3 ? (int)blockIdx.z : 0;
-  if (x >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);  // y + n z
+  const int rows = DIM == 3 ? n * n : n;
+  if (row >= rows) return;
+  const int y = row % n;
+  const int z = DIM == 3 ? row / n : 0;
   auto inside = [&](int zz, int yy, int xx) {
     return xx >= 1 && xx <= n - 2 && yy >= 1 && yy <= n - 2 &&
            (DIM == 2 || (zz >= 1 && zz <= n - 2));
   };
-  const size_t j = ((size_t)z * n + y) * (size_t)n + x;
-  const bool jin = inside(z, y, x);
-  const double lj = jin ? lam[j] : 0.0;
-  const double uj = u[j];
-  if (dk) {
-    const int nz[6] = {z, z, z, z, z - 1, z + 1};
-    const int ny[6] = {y, y, y - 1, y + 1, y, y};
-    const int nx[6] = {x - 1, x + 1, x, x, x, x};
-    double s = 0.0;
+  for (int x = lane; x < n; x += 64) {
+    const size_t j = ((size_t)z * n + y) * (size_t)n + x;
+    const bool jin = inside(z, y, x);
+    const double lj = jin ? lam[j] : 0.0;
+    const double uj = u[j];
+    if (dk) {
+      const int nz[6] = {z, z, z, z, z - 1, z + 1};
+      const int ny[6] = {y, y, y - 1, y + 1, y, y};
+      const int nx[6] = {x - 1, x + 1, x, x, x, x};
+      double s = 0.0;
 #pragma unroll
-    for (int a = 0; a < 2 * DIM; ++a) {
-      if (nx[a] < 0 || nx[a] >= n || ny[a] < 0 || ny[a] >= n) continue;
-      if (DIM == 3 && (nz[a] < 0 || nz[a] >= n)) continue;
-      const size_t b = ((size_t)(DIM == 3 ? nz[a] : 0) * n + ny[a]) * (size_t)n + nx[a];
-      const double lb = inside(nz[a], ny[a], nx[a]) ? lam[b] : 0.0;
-      s += (lj - lb) * (uj - u[b]);
+      for (int a = 0; a < 2 * DIM; ++a) {
+        if (nx[a] < 0 || nx[a] >= n || ny[a] < 0 || ny[a] >= n) continue;
+        if (DIM == 3 && (nz[a] < 0 || nz[a] >= n)) continue;
+        const size_t b = ((size_t)(DIM == 3 ? nz[a] : 0) * n + ny[a]) * (size_t)n + nx[a];
+        const double lb = inside(nz[a], ny[a], nx[a]) ? lam[b] : 0.0;
+        s += (lj - lb) * (uj - u[b]);
+      }
+      dk[j] = c * s;
     }
-    dk[j] = c * s;
+    if (df) df[j] = jin ? lj : 0.0;
   }
-  if (df) df[j] = jin ? lj : 0.0;
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -539,12 +545,12 @@ void cast_to_f32(hipStream_t s, size_t count, const double* src, float* dst)
 void grad(hipStream_t s, int dim, int n, const double* u, const double* lam, double* dk,
           double* df)
 {
-  const int bx = n >= 256 ? 256 : 64;
-  const dim3 grid(cdiv(n, bx), n, dim == 3 ? n : 1);
+  const int rows = dim == 3 ? n * n : n;
+  const dim3 grid(cdiv(rows, kBlock / 64));
   const double h = 1.0 / (double)(n - 1);
   const double c = -1.0 / (2.0 * h * h);
-  if (dim == 3) k_grad<3><<<grid, bx, 0, s>>>(u, lam, dk, df, n, c);
-  else k_grad<2><<<grid, bx, 0, s>>>(u, lam, dk, df, n, c);
+  if (dim == 3) k_grad<3><<<grid, kBlock, 0, s>>>(u, lam, dk, df, n, c);
+  else k_grad<2><<<grid, kBlock, 0, s>>>(u, lam, dk, df, n, c);
 }
 
 template <typename T>
