@@ -351,6 +351,56 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// The 3D gradient pass marching along z: a workgroup covers 64 x 4 nodes of a plane and
+// kGradZ planes; every thread keeps u and lambda of the planes z-1, z, z+1 in registers, so
+// each node is fetched from HBM once, its in-plane neighbours from the caches.  Same terms in
+// the same order as k_grad.
+constexpr int kGradZ = 32;
+
+__global__ void __launch_bounds__(kBlock)
+    k_grad3_march(const double* __restrict__ u, const double* __restrict__ lam,
+                  double* __restrict__ dk, double* __restrict__ df, int n, double c)
+{
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int z0 = blockIdx.z * kGradZ, z1 = min(z0 + kGradZ, n);
+  if (x >= n || y >= n) return;  // no barrier below
+  const size_t plane = (size_t)n * n, col = (size_t)y * n + x;
+  auto inside = [&](int zz, int yy, int xx) {
+    return xx >= 1 && xx <= n - 2 && yy >= 1 && yy <= n - 2 && zz >= 1 && zz <= n - 2;
+  };
+  auto lam_at = [&](int zz, int yy, int xx, size_t i) { return inside(zz, yy, xx) ? lam[i] : 0.0; };
+  double um = 0.0, lm = 0.0;  // plane z-1
+  if (z0 > 0) {
+    um = u[(size_t)(z0 - 1) * plane + col];
+    lm = lam_at(z0 - 1, y, x, (size_t)(z0 - 1) * plane + col);
+  }
+  double uc = u[(size_t)z0 * plane + col], lc = lam_at(z0, y, x, (size_t)z0 * plane + col);
+  for (int z = z0; z < z1; ++z) {
+    const size_t j = (size_t)z * plane + col;
+    double up = 0.0, lp = 0.0;  // plane z+1
+    if (z + 1 < n) {
+      up = u[j + plane];
+      lp = lam_at(z + 1, y, x, j + plane);
+    }
+    if (dk) {
+      double s = 0.0;
+      if (x - 1 >= 0) s += (lc - lam_at(z, y, x - 1, j - 1)) * (uc - u[j - 1]);
+      if (x + 1 < n) s += (lc - lam_at(z, y, x + 1, j + 1)) * (uc - u[j + 1]);
+      if (y - 1 >= 0) s += (lc - lam_at(z, y - 1, x, j - n)) * (uc - u[j - n]);
+      if (y + 1 < n) s += (lc - lam_at(z, y + 1, x, j + n)) * (uc - u[j + n]);
+      if (z - 1 >= 0) s += (lc - lm) * (uc - um);
+      if (z + 1 < n) s += (lc - lp) * (uc - up);
+      dk[j] = c * s;
+    }
+    if (df) df[j] = inside(z, y, x) ? lc : 0.0;
+    um = uc;
+    lm = lc;
+    uc = up;
+    lc = lp;
+  }
+}
+
 // ------------------------------------------------------------------ small helpers
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, size_t count, T v)
@@ -545,12 +595,14 @@ void cast_to_f32(hipStream_t s, size_t count, const double* src, float* dst)
 void grad(hipStream_t s, int dim, int n, const double* u, const double* lam, double* dk,
           double* df)
 {
-  const int rows = dim == 3 ? n * n : n;
-  const dim3 grid(cdiv(rows, kBlock / 64));
   const double h = 1.0 / (double)(n - 1);
   const double c = -1.0 / (2.0 * h * h);
-  if (dim == 3) k_grad<3><<<grid, kBlock, 0, s>>>(u, lam, dk, df, n, c);
-  else k_grad<2><<<grid, kBlock, 0, s>>>(u, lam, dk, df, n, c);
+  if (dim == 3) {
+    const dim3 grid(cdiv(n, 64), cdiv(n, 4), cdiv(n, kGradZ));
+    k_grad3_march<<<grid, kBlock, 0, s>>>(u, lam, dk, df, n, c);
+  } else {
+    k_grad<2><<<dim3(cdiv(n, kBlock / 64)), kBlock, 0, s>>>(u, lam, dk, df, n, c);
+  }
 }
 
 template <typename T>
