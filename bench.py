@@ -344,11 +344,11 @@ def galerkin_benchmark(dev, sizes=((257, 8, 4), (513, 9, 5))):
         k = torch.from_numpy(inputs.lognormal_k(3, n, seed=seed)).to(dev)
         f = torch.from_numpy(inputs.constant_interior(3, n)).to(dev)
         rec = {}
-        for name in ("galerkin", "rediscretised"):
+        for name in ("galerkin", "galerkin_f32_stencils", "rediscretised"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if name == "galerkin":
-                mg = GalerkinMultigrid(k, levels)
+            if name.startswith("galerkin"):
+                mg = GalerkinMultigrid(k, levels, coarse_f32=name.endswith("f32_stencils"))
             else:
                 mg = Multigrid(3, n, levels, variable=True, device=dev)
                 mg.set_coefficients(k)
@@ -367,13 +367,15 @@ def galerkin_benchmark(dev, sizes=((257, 8, 4), (513, 9, 5))):
                          "relres": info.relres, "solve_ms": round(float(np.min(ms)), 2)}
             if name == "galerkin":
                 ug = u.clone()
-            else:
+            elif name == "rediscretised":
                 rec["solution_rel_diff"] = float((ug - u).abs().max() / u.abs().max())
             mg.close()
             del mg, u
         out[str(n)] = rec
         print(f"bench: galerkin n={n}: {rec['galerkin']['cycles']} cycles {rec['galerkin']['solve_ms']} ms "
-              f"(setup {rec['galerkin']['setup_ms']} ms); rediscretised {rec['rediscretised']['cycles']} cycles "
+              f"(setup {rec['galerkin']['setup_ms']} ms); with FP32 coarse stencils "
+              f"{rec['galerkin_f32_stencils']['cycles']} cycles {rec['galerkin_f32_stencils']['solve_ms']} ms; "
+              f"rediscretised {rec['rediscretised']['cycles']} cycles "
               f"{rec['rediscretised']['solve_ms']} ms", file=sys.stderr, flush=True)
         del k, f, ug
         torch.cuda.empty_cache()

@@ -43,6 +43,9 @@ typedef struct {
   int levels;      /* must reach n_{levels-1} = 3 */
   int nu1, nu2;    /* sweeps per level (2, 2) */
   int max_cycles;  /* mggal_solve: cycle limit */
+  int coarse_f32;  /* 1: the cycle's 27-point kernels read an FP32 copy of the coarse stencils
+                      (built in FP64; half the coefficient traffic; the coarse levels only
+                      compute corrections, the fine level and the stopping test stay FP64) */
 } mggal_grid;
 
 /* Bytes of device workspace (host-only); 0 if the description is invalid. */

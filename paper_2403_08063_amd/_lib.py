@@ -61,7 +61,7 @@ class MgBlkGrid(ctypes.Structure):
 
 class MgGalGrid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("levels", ctypes.c_int), ("nu1", ctypes.c_int),
-                ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int)]
+                ("nu2", ctypes.c_int), ("max_cycles", ctypes.c_int), ("coarse_f32", ctypes.c_int)]
 
 
 class MgError(RuntimeError):

@@ -43,14 +43,16 @@ __device__ __forceinline__ size_t slot_of(int half, int z, int y, int x)
 }
 
 // first coefficient (offset 0) of interior node (z, y, x); offset o at + o * half^3
-__device__ __forceinline__ const double* node_coeffs(const double* S, int half, int z, int y, int x)
+template <typename TS>
+__device__ __forceinline__ const TS* node_coeffs(const TS* S, int half, int z, int y, int x)
 {
   const size_t h3 = (size_t)half * half * half;
   return S + (size_t)colour_of(z, y, x) * 27 * h3 + slot_of(half, z, y, x);
 }
 
 // (A u)_i - a_ii u_i: the off-diagonal part of the 27-point stencil at interior node i
-__device__ __forceinline__ double offdiag(const double* __restrict__ Sn, size_t h3,
+template <typename TS>
+__device__ __forceinline__ double offdiag(const TS* __restrict__ Sn, size_t h3,
                                           const double* __restrict__ u, int n, int z, int y, int x)
 {
   double s = 0.0;
@@ -58,14 +60,15 @@ __device__ __forceinline__ double offdiag(const double* __restrict__ Sn, size_t 
   for (int o = 0; o < 27; ++o) {
     if (o == kCentre) continue;
     const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
-    s += Sn[o * h3] * u[gidx(n, z + dz, y + dy, x + dx)];
+    s += (double)Sn[o * h3] * u[gidx(n, z + dz, y + dy, x + dx)];
   }
   return s;
 }
 
 // one colour of eight-colour Gauss-Seidel: nodes with parities (pz, py, px) of colour c
+template <typename TS>
 __global__ void __launch_bounds__(kGalThreads)
-    k_gal_gs(int n, const double* __restrict__ S, const double* __restrict__ f, double* u, int c)
+    k_gal_gs(int n, const TS* __restrict__ S, const double* __restrict__ f, double* u, int c)
 {
   const int half = (n - 1) / 2;
   const int t = blockIdx.x * kGalThreads + threadIdx.x;
@@ -75,14 +78,15 @@ __global__ void __launch_bounds__(kGalThreads)
   const int x = 2 * (t % half) + 2 - px, y = 2 * ((t / half) % half) + 2 - py, z = 2 * (t / (half * half)) + 2 - pz;
   if (x > n - 2 || y > n - 2 || z > n - 2) return;
   const size_t h3 = (size_t)half * half * half;
-  const double* Sn = S + (size_t)c * 27 * h3 + t;
+  const TS* Sn = S + (size_t)c * 27 * h3 + t;
   const size_t i = gidx(n, z, y, x);
-  u[i] = (f[i] - offdiag(Sn, h3, u, n, z, y, x)) / Sn[kCentre * h3];
+  u[i] = (f[i] - offdiag(Sn, h3, u, n, z, y, x)) / (double)Sn[kCentre * h3];
 }
 
 // r = f - A u at interior nodes (f == nullptr reads 0); the boundary of r is not written
+template <typename TS>
 __global__ void __launch_bounds__(kGalThreads)
-    k_gal_residual(int n, const double* __restrict__ S, const double* __restrict__ f,
+    k_gal_residual(int n, const TS* __restrict__ S, const double* __restrict__ f,
                    const double* __restrict__ u, double* __restrict__ r)
 {
   const int m = n - 2;
@@ -91,9 +95,9 @@ __global__ void __launch_bounds__(kGalThreads)
   const int x = 1 + t % m, y = 1 + (t / m) % m, z = 1 + t / (m * m);
   const int half = (n - 1) / 2;
   const size_t h3 = (size_t)half * half * half;
-  const double* Sn = node_coeffs(S, half, z, y, x);
+  const TS* Sn = node_coeffs(S, half, z, y, x);
   const size_t i = gidx(n, z, y, x);
-  const double au = Sn[kCentre * h3] * u[i] + offdiag(Sn, h3, u, n, z, y, x);
+  const double au = (double)Sn[kCentre * h3] * u[i] + offdiag(Sn, h3, u, n, z, y, x);
   r[i] = (f ? f[i] : 0.0) - au;
 }
 
@@ -143,6 +147,13 @@ __global__ void __launch_bounds__(kGalThreads)
   const_cast<double*>(node_coeffs(S, half, Z, Y, X))[o * h3] = -fc[gidx(nc, Z, Y, X)];
 }
 
+__global__ void __launch_bounds__(kGalThreads)
+    k_gal_to_f32(const double* __restrict__ S, float* __restrict__ S32, size_t count)
+{
+  const size_t t = (size_t)blockIdx.x * kGalThreads + threadIdx.x;
+  if (t < count) S32[t] = (float)S[t];
+}
+
 // the coarsest level (3^3 nodes): its one interior node (colour 7, slot 0 of one)
 __global__ void k_gal_coarsest(const double* __restrict__ S, const double* __restrict__ f,
                                double* __restrict__ u)
@@ -178,6 +189,7 @@ struct GalLevel {
   double* f = nullptr;  // right-hand side (levels >= 1)
   double* r = nullptr;  // residual (levels >= 1)
   double* S = nullptr;  // colour-major stencil (levels >= 1)
+  float* S32 = nullptr; // its FP32 copy for the cycle (coarse_f32)
 };
 
 struct mggal_ctx {
@@ -223,6 +235,7 @@ mg_status gal_validate(const mggal_grid* g)
     return gal_fail(nullptr, MG_EINVAL, "levels must reach 3 nodes per side (n=%d, levels=%d)", n, g->levels);
   if (g->nu1 < 0 || g->nu2 < 0) return gal_fail(nullptr, MG_EINVAL, "nu1, nu2 must be >= 0");
   if (g->max_cycles < 1) return gal_fail(nullptr, MG_EINVAL, "max_cycles must be >= 1");
+  if (g->coarse_f32 != 0 && g->coarse_f32 != 1) return gal_fail(nullptr, MG_EINVAL, "coarse_f32 must be 0 or 1");
   return MG_OK;
 }
 
@@ -260,6 +273,7 @@ void gal_layout(const mggal_grid* g, GalCarver& cv, mggal_ctx* c)
       L.f = cv.take<double>(L.cnt);
       L.r = cv.take<double>(L.cnt);
       L.S = cv.take<double>(L.scnt);
+      if (g->coarse_f32) L.S32 = cv.take<float>(L.scnt);
     }
     lv.push_back(L);
     n = (n - 1) / 2 + 1;
@@ -300,8 +314,11 @@ void smooth(mggal_ctx* c, int l, const double* f, double* u, int sweeps)
       mgk::rbgs_colour<double>(c->s, 3, L.n, c->h, c->k, f, u, 1);
     } else {
       const int half = (L.n - 1) / 2;
-      for (int col = 0; col < 8; ++col)
-        k_gal_gs<<<blocks_for((size_t)half * half * half), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, col);
+      for (int col = 0; col < 8; ++col) {
+        const unsigned gb = blocks_for((size_t)half * half * half);
+        if (L.S32) k_gal_gs<float><<<gb, kGalThreads, 0, c->s>>>(L.n, L.S32, f, u, col);
+        else k_gal_gs<double><<<gb, kGalThreads, 0, c->s>>>(L.n, L.S, f, u, col);
+      }
     }
   }
 }
@@ -315,7 +332,9 @@ void restrict_to(mggal_ctx* c, int l, const double* f, const double* u, double* 
     else mgk::restrict_residual<double>(c->s, 3, L.n, c->h, c->k, f ? f : c->zero, u, fc);
   } else {
     const size_t mf = (size_t)L.n - 2, mc = (size_t)c->lv[l + 1].n - 2;
-    k_gal_residual<<<blocks_for(mf * mf * mf), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, L.r);
+    // the probes that build the hierarchy always run with the FP64 stencil
+    if (L.S32 && f) k_gal_residual<float><<<blocks_for(mf * mf * mf), kGalThreads, 0, c->s>>>(L.n, L.S32, f, u, L.r);
+    else k_gal_residual<double><<<blocks_for(mf * mf * mf), kGalThreads, 0, c->s>>>(L.n, L.S, f, u, L.r);
     k_gal_fw<<<blocks_for(mc * mc * mc), kGalThreads, 0, c->s>>>(L.n, L.r, fc);
   }
 }
@@ -406,6 +425,9 @@ mg_status mggal_setup(const mggal_grid* grid, const double* k, void* workspace, 
     mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, c->lv[l].r);
   }
   for (size_t l = 0; l + 1 < c->lv.size(); ++l) build_level(c, (int)l);
+  for (size_t l = 1; l < c->lv.size(); ++l)
+    if (c->lv[l].S32)
+      k_gal_to_f32<<<blocks_for(c->lv[l].scnt), kGalThreads, 0, c->s>>>(c->lv[l].S, c->lv[l].S32, c->lv[l].scnt);
   mg_status st = gal_hip(c, hipGetLastError(), "building the Galerkin hierarchy");
   if (!st) st = gal_hip(c, hipStreamSynchronize(c->s), "setup");
   if (st) {

@@ -20,7 +20,7 @@ class GalerkinMultigrid:
     """Galerkin hierarchy of the coefficient k (n^3 node values > 0) on `device`."""
 
     def __init__(self, k: torch.Tensor, levels: int | None = None, nu1: int = 2, nu2: int = 2,
-                 max_cycles: int = 100):
+                 max_cycles: int = 100, coarse_f32: bool = False):
         if not isinstance(k, torch.Tensor) or k.dtype != torch.float64 or k.dim() != 3:
             raise TypeError("k must be a 3D float64 torch tensor")
         if k.device.type != "cuda":
@@ -29,7 +29,7 @@ class GalerkinMultigrid:
         # by default down to 3 nodes per side: n = 2^m + 1 has m levels
         self.levels = int(levels) if levels is not None else max(2, (self.n - 1).bit_length() - 1)
         self.device = k.device
-        self.grid = MgGalGrid(self.n, self.levels, int(nu1), int(nu2), int(max_cycles))
+        self.grid = MgGalGrid(self.n, self.levels, int(nu1), int(nu2), int(max_cycles), int(bool(coarse_f32)))
         L = lib()
         self.workspace_bytes = int(L.mggal_workspace_bytes(ctypes.byref(self.grid)))
         if self.workspace_bytes == 0:

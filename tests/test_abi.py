@@ -173,13 +173,15 @@ def gal_bytes(**kw):
     return _lib.lib().mggal_workspace_bytes(ctypes.byref(MgGalGrid(**g)))
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(n=5, levels=2), dict(n=257, levels=8), dict(nu1=0)])
+@pytest.mark.parametrize("kw", [dict(), dict(n=5, levels=2), dict(n=257, levels=8), dict(nu1=0),
+                                dict(coarse_f32=1)])
 def test_gal_valid_grids(kw):
     assert gal_bytes(**kw) > 0
 
 
 @pytest.mark.parametrize("kw", [dict(n=32), dict(n=3, levels=1), dict(levels=4), dict(levels=6),
-                                dict(nu1=-1), dict(max_cycles=0), dict(n=2049, levels=11)])
+                                dict(nu1=-1), dict(max_cycles=0), dict(n=2049, levels=11),
+                                dict(coarse_f32=2)])
 def test_gal_invalid_grids_need_no_workspace(kw):
     assert gal_bytes(**kw) == 0
 
@@ -197,6 +199,10 @@ def test_gal_workspace_size():
         want += 3 * al(nl ** 3 * 8) + al(8 * 27 * ((nl - 1) // 2) ** 3 * 8)
     got = gal_bytes(n=n, levels=levels)
     assert want <= got <= want + 16384 * 8 + 4 * 256
+    # the FP32 copies of the coarse stencils: half their FP64 size more
+    extra = sum(-(-(8 * 27 * ((((n - 1) >> l) + 1 - 1) // 2) ** 3 * 4) // 256) * 256 for l in range(1, levels))
+    # (each array starts on a 256-byte boundary, so the padding may shift by < 256 per array)
+    assert abs(gal_bytes(n=n, levels=levels, coarse_f32=1) - (got + extra)) < 256 * 4 * levels
 
 
 def test_block_and_galerkin_entry_points_reject_bad_arguments_before_gpu_work():

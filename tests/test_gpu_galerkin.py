@@ -162,3 +162,24 @@ def test_nonzero_dirichlet_data_matches_rediscretised_solution():
     assert np.array_equal(u1.cpu().numpy()[0], ub[0]) and np.array_equal(u1.cpu().numpy()[:, :, -1], ub[:, :, -1])
     assert (u1 - u2).abs().max().item() <= 1e-9 * u2.abs().max().item()
     mg.close()
+
+
+@pytest.mark.parametrize("n,levels", [(65, 6), (257, 8)])
+def test_fp32_coarse_stencils_reach_the_same_solution(n, levels):
+    """With FP32 copies of the coarse stencils the cycle's corrections change by rounding only:
+    the solve reaches 1e-10 in at most one cycle more and the solution agrees with the
+    FP64-stencil solve to the tolerance's order."""
+    say(f"galerkin FP32 coarse stencils n={n}")
+    k = to_gpu(inputs.lognormal_k(3, n, seed=4))
+    f = to_gpu(inputs.constant_interior(3, n))
+    m64 = GalerkinMultigrid(k, levels)
+    u64, i64 = m64.solve(f, tol=1e-10)
+    m32 = GalerkinMultigrid(k, levels, coarse_f32=True)
+    u32, i32 = m32.solve(f, tol=1e-10)
+    say(f"  cycles fp64 stencils {i64.cycles}, fp32 stencils {i32.cycles}")
+    assert i64.converged and i32.converged and i32.cycles <= i64.cycles + 1
+    assert (u32 - u64).abs().max().item() <= 1e-9 * u64.abs().max().item()
+    # the exported stencil is the FP64 one
+    assert torch.equal(m32.stencil(1), m64.stencil(1))
+    m64.close()
+    m32.close()
