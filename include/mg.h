@@ -175,8 +175,31 @@ enum {
 };
 mg_status mg_set_fusion(mg_ctx* ctx, int flags);
 
+/* ---- allocation-free solve ----
+ * For callers that cannot allocate device memory or set up a context at the time of the
+ * solve (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): mg_solve on a context built for this one call, whose workspace is a static
+ * device array of MG_NOALLOC_MAX_BYTES inside the library instead of a caller-allocated
+ * one.  The call makes no device or host allocation of any kind (no hipMalloc, hipFree,
+ * pinned memory or heap); FP32-refined solves read their norms synchronously.
+ *   grid:   as for mg_setup; mg_workspace_bytes(grid) must not exceed MG_NOALLOC_MAX_BYTES
+ *           (else MG_ENOMEM, before any HIP call).  32 MiB holds e.g. a 129^3 FP64 or a
+ *           65^3 FP32-refined variable-coefficient grid.
+ *   k:      variable-coefficient grids: device array of n^d values > 0; NULL otherwise.
+ *   f, u, tol, cycles, relres: as for mg_solve (u in/out, boundary = Dirichlet data).
+ *   stream: hipStream_t (or NULL) of the current HIP device, which must hold k, f and u.
+ * Results are those of mg_setup + mg_set_coefficients + mg_solve with the same arguments
+ * (the same kernels in the same order).  The static array exists once per GPU, from the
+ * first call on that GPU until the process ends, and keeps the last call's contents; each
+ * call re-initialises the part it uses.  Calls that overlap on one GPU (other threads,
+ * other streams) race on it.  The stream is synchronised once per cycle, as by mg_solve.
+ * Errors are reported by mg_last_error(NULL). */
+#define MG_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+mg_status mg_solve_noalloc(const mg_grid* grid, const double* k, const double* f, double* u,
+                           double tol, void* stream, int* cycles, double* relres);
+
 /* Message for the last failing call on ctx, or for the last failing mg_setup /
- * mg_validate call of this thread when ctx is NULL.  Never NULL. */
+ * mg_validate / mg_solve_noalloc call of this thread when ctx is NULL.  Never NULL. */
 const char* mg_last_error(const mg_ctx* ctx);
 
 /* Releases the context (not the workspace).  Does not synchronise. */

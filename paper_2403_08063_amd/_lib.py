@@ -15,6 +15,7 @@ MG_OK, MG_EINVAL, MG_ENOMEM, MG_EHIP, MG_ENOCONV, MG_ENAN, MG_ESTATE = range(7)
 STATUS_NAMES = {0: "MG_OK", 1: "MG_EINVAL", 2: "MG_ENOMEM", 3: "MG_EHIP", 4: "MG_ENOCONV",
                 5: "MG_ENAN", 6: "MG_ESTATE"}
 MG_F64, MG_F32_IR = 0, 1
+NOALLOC_MAX_BYTES = 32 << 20  # MG_NOALLOC_MAX_BYTES of include/mg.h
 # kernel-fusion flags (mg_set_fusion)
 FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL, FUSE_RESTRICT = 1, 2, 4, 8, 16
 FUSE_ALL = 31
@@ -25,7 +26,7 @@ EXPORTS = [
     "mg_solve", "mg_solve_adjoint", "mg_grad", "mg_smooth", "mg_smooth_f32", "mg_residual",
     "mg_restrict_residual", "mg_restrict_residual_f32", "mg_prolong_correct",
     "mg_prolong_correct_f32", "mg_coarsest_solve", "mg_residual_norm2",
-    "mg_set_fusion", "mg_last_error", "mg_destroy",
+    "mg_set_fusion", "mg_solve_noalloc", "mg_last_error", "mg_destroy",
     # include/mg_fv.h
     "mgfv_workspace_bytes", "mgfv_setup", "mgfv_destroy", "mgfv_last_error", "mgfv_jacobi",
     "mgfv_residual", "mgfv_restrict_residual", "mgfv_prolong_correct", "mgfv_coarse_solve",
@@ -107,6 +108,7 @@ def lib() -> ctypes.CDLL:
         "mg_coarsest_solve": (i, [P, P, P]),
         "mg_residual_norm2": (i, [P, P, P, PD]),
         "mg_set_fusion": (i, [P, i]),
+        "mg_solve_noalloc": (i, [G, P, P, P, d, P, PI, PD]),
         "mg_last_error": (ctypes.c_char_p, [P]),
         "mg_destroy": (None, [P]),
         "mgfv_workspace_bytes": (S, [FG]),

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 
@@ -554,6 +555,81 @@ mg_status smooth_impl(mg_ctx* c, int level, const T* f, T* u, int sweeps)
   return launch_check(c, "smoothing");
 }
 
+// Lays a context out on `workspace` (`need` bytes) and enqueues the workspace's
+// initialisation: shared by mg_setup and mg_solve_noalloc.
+mg_status init_ctx(mg_ctx* c, const mg_grid* grid, void* workspace, size_t need, hipStream_t s)
+{
+  c->g = *grid;
+  c->s = s;
+  Carver cv{static_cast<char*>(workspace)};
+  layout(grid, cv, c);
+  for (int l = 1; l + 1 < grid->levels && l - 1 < mgk::kMaxTail; ++l)
+    if (mgk::tail_fits(grid->dim, c->lv[l].n) && grid->levels - l <= mgk::kMaxTail) {
+      c->tail_first = l;
+      break;
+    }
+  // zero the whole workspace once: coarse boundaries (zero Dirichlet data of corrections)
+  // and the boundaries of the second buffers are never written afterwards
+  mgk::fill<double>(c->s, need / sizeof(double), 0.0, static_cast<double*>(workspace));
+  if (!grid->variable) {
+    const Level& Lc = c->lv[grid->levels - 1];
+    mgk::coarsest_factor(c->s, grid->dim, Lc.n, Lc.h, nullptr, c->chol, c->ainv, c->flag);
+  }
+  return launch_check(c, "setup");
+}
+
+// Copies k into the workspace and builds the coefficient hierarchy and the coarsest factor.
+mg_status set_coefficients_impl(mg_ctx* c, const double* k)
+{
+  const int dim = c->g.dim;
+  mgk::copy<double>(c->s, c->lv[0].N, k, c->lv[0].k);
+  for (int l = 1; l < c->g.levels; ++l) mgk::coarsen_k(c->s, dim, c->lv[l - 1].n, c->lv[l - 1].k, c->lv[l].k);
+  if (c->g.precision == MG_F32_IR)
+    for (int l = 0; l < c->g.levels; ++l) mgk::cast_to_f32(c->s, c->lv[l].N, c->lv[l].k, c->lv[l].k32);
+  const Level& Lc = c->lv[c->g.levels - 1];
+  mgk::coarsest_factor(c->s, dim, Lc.n, Lc.h, Lc.k, c->chol, c->ainv, c->flag);
+  if (mg_status st = launch_check(c, "set_coefficients")) return st;
+  c->coeffs = true;
+  return MG_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------- device memory of mg_solve_noalloc
+// A file-scope array: every GPU the library runs on holds its own copy from the loading of
+// this code object there until the process ends.  In host code the name `scratch` is only a
+// host-side stand-in, never a device address: host code uses the address that
+// hipGetSymbolAddress returns for the current device (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[MG_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per device with
+// that device current.
+mg_status scratch_address(void** out)
+{
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, MG_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(nullptr, MG_EINVAL, "device %d: at most %d devices are supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, MG_EHIP, "hipGetSymbolAddress of the static scratch array: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MG_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -582,25 +658,10 @@ mg_status mg_setup(const mg_grid* grid, void* workspace, size_t bytes, void* str
     return fail(nullptr, MG_ENOMEM, "workspace of %zu bytes < %zu required", bytes, need);
   mg_ctx* c = new (std::nothrow) mg_ctx;
   if (!c) return fail(nullptr, MG_ENOMEM, "host allocation of the context failed");
-  c->g = *grid;
-  c->s = static_cast<hipStream_t>(stream);
-  Carver cv{static_cast<char*>(workspace)};
-  layout(grid, cv, c);
-  for (int l = 1; l + 1 < grid->levels && l - 1 < mgk::kMaxTail; ++l)
-    if (mgk::tail_fits(grid->dim, c->lv[l].n) && grid->levels - l <= mgk::kMaxTail) {
-      c->tail_first = l;
-      break;
-    }
-  // zero the whole workspace once: coarse boundaries (zero Dirichlet data of corrections)
-  // and the boundaries of the second buffers are never written afterwards
-  mgk::fill<double>(c->s, need / sizeof(double), 0.0, static_cast<double*>(workspace));
-  if (!grid->variable) {
-    const Level& Lc = c->lv[grid->levels - 1];
-    mgk::coarsest_factor(c->s, grid->dim, Lc.n, Lc.h, nullptr, c->chol, c->ainv, c->flag);
-  }
+  mg_status st = init_ctx(c, grid, workspace, need, static_cast<hipStream_t>(stream));
   // one pinned host word for overlapped norm reads (FP32 refinement); without it the solve
   // reads synchronously
-  if (grid->precision == MG_F32_IR) {
+  if (!st && grid->precision == MG_F32_IR) {
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 64, hipHostMallocDefault) == hipSuccess) {
       c->hnorm = static_cast<double*>(hp);
@@ -608,7 +669,7 @@ mg_status mg_setup(const mg_grid* grid, void* workspace, size_t bytes, void* str
     }
     (void)hipGetLastError();  // a failed pinned allocation only disables the overlap
   }
-  if (mg_status st = launch_check(c, "setup")) {
+  if (st) {
     snprintf(g_err, sizeof g_err, "%s", c->err);
     delete c;
     return st;
@@ -622,16 +683,7 @@ mg_status mg_set_coefficients(mg_ctx* c, const double* k)
   if (!c) return fail(nullptr, MG_EINVAL, "context is NULL");
   if (!c->g.variable) return fail(c, MG_ESTATE, "constant-coefficient context");
   if (!k) return fail(c, MG_EINVAL, "k is NULL");
-  const int dim = c->g.dim;
-  mgk::copy<double>(c->s, c->lv[0].N, k, c->lv[0].k);
-  for (int l = 1; l < c->g.levels; ++l) mgk::coarsen_k(c->s, dim, c->lv[l - 1].n, c->lv[l - 1].k, c->lv[l].k);
-  if (c->g.precision == MG_F32_IR)
-    for (int l = 0; l < c->g.levels; ++l) mgk::cast_to_f32(c->s, c->lv[l].N, c->lv[l].k, c->lv[l].k32);
-  const Level& Lc = c->lv[c->g.levels - 1];
-  mgk::coarsest_factor(c->s, dim, Lc.n, Lc.h, Lc.k, c->chol, c->ainv, c->flag);
-  if (mg_status st = launch_check(c, "set_coefficients")) return st;
-  c->coeffs = true;
-  return MG_OK;
+  return set_coefficients_impl(c, k);
 }
 
 mg_status mg_vcycle(mg_ctx* c, const double* f, double* u)
@@ -746,6 +798,31 @@ mg_status mg_residual_norm2(mg_ctx* c, const double* f, const double* u, double*
   norm2(c, f, u, 0, 0);
   if (mg_status st = launch_check(c, "norm")) return st;
   return read_scalar(c, c->scal, out);
+}
+
+mg_status mg_solve_noalloc(const mg_grid* grid, const double* k, const double* f, double* u,
+                           double tol, void* stream, int* cycles, double* relres)
+{
+  // every argument is checked before the first HIP call
+  if (mg_status st = validate(grid, nullptr)) return st;
+  if (grid->variable && !k) return fail(nullptr, MG_EINVAL, "variable-coefficient grid: k is NULL");
+  if (!grid->variable && k) return fail(nullptr, MG_EINVAL, "k given for a constant-coefficient grid");
+  if (!f || !u) return fail(nullptr, MG_EINVAL, "f and u must be non-NULL");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(nullptr, MG_EINVAL, "tol must be > 0");
+  const size_t need = mg_workspace_bytes(grid);
+  if (need > MG_NOALLOC_MAX_BYTES)
+    return fail(nullptr, MG_ENOMEM,
+                "grid needs %zu bytes of device workspace, more than the %zu bytes of the "
+                "allocation-free solve: use mg_setup with a workspace", need,
+                (size_t)MG_NOALLOC_MAX_BYTES);
+  void* ws = nullptr;
+  if (mg_status st = scratch_address(&ws)) return st;
+  mg_ctx c;  // on the stack: no host allocation either (no pinned word: synchronous norm reads)
+  mg_status st = init_ctx(&c, grid, ws, need, static_cast<hipStream_t>(stream));
+  if (!st && grid->variable) st = set_coefficients_impl(&c, k);
+  if (!st) st = solve_impl(&c, f, u, tol, cycles, relres);
+  if (st) snprintf(g_err, sizeof g_err, "%s", c.err);
+  return st;
 }
 
 mg_status mg_set_fusion(mg_ctx* c, int flags)

@@ -38,6 +38,41 @@ def default_levels(n: int, dim: int = 3) -> int:
     return levels
 
 
+def solve_noalloc(f, u, k=None, levels: int | None = None, nu1: int = 2, nu2: int = 2,
+                  max_cycles: int = 100, precision: str = "f64", tol: float = 1e-10,
+                  raise_on_noconv: bool = True):
+    """``mg_solve_noalloc``: one solve of A u = f whose device workspace is the library's
+    static array (no allocation by the library; grids up to ``_lib.NOALLOC_MAX_BYTES`` of
+    workspace).  f, u (in/out initial guess, boundary = Dirichlet data) and k (variable
+    coefficient, or None) are float64 tensors of n^dim values on the current device; the
+    call runs on torch's current stream.  -> (u, SolveInfo)"""
+    if precision not in ("f64", "f32_ir"):
+        raise ValueError("precision must be 'f64' or 'f32_ir'")
+    dim, n = f.dim(), int(f.shape[0])
+    for name, t in (("f", f), ("u", u), ("k", k)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 torch tensor")
+        if t.device.type != "cuda" or t.device != f.device:
+            raise ValueError(f"{name} must be on the device of f")
+        if not t.is_contiguous() or tuple(t.shape) != (n,) * dim:
+            raise ValueError(f"{name} must be a contiguous {n}^{dim} tensor")
+    levels = default_levels(n, dim) if levels is None else int(levels)
+    grid = MgGrid(dim, n, levels, int(nu1), int(nu2), int(max_cycles),
+                  MG_F32_IR if precision == "f32_ir" else MG_F64, int(k is not None))
+    cyc, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+    allow = () if raise_on_noconv else (MG_ENOCONV,)
+    with torch.cuda.device(f.device):
+        stream = torch.cuda.current_stream(f.device)
+        st = check(lib().mg_solve_noalloc(
+            ctypes.byref(grid), None if k is None else ctypes.c_void_p(k.data_ptr()),
+            ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), float(tol),
+            ctypes.c_void_p(stream.cuda_stream), ctypes.byref(cyc), ctypes.byref(rel)),
+            None, allow)
+    return u, SolveInfo(cyc.value, rel.value, st)
+
+
 class Multigrid:
     """Geometric multigrid for -Laplace(u) = f (or -div(k grad u) = f) on an n^dim node grid.
 

@@ -238,3 +238,25 @@ def test_block_and_galerkin_entry_points_reject_bad_arguments_before_gpu_work():
                  lambda: lib.mggal_solve(None, None, None, 1e-10, None, None),
                  lambda: lib.mggal_stencil(None, 1, None)):
         assert call() == MG_EINVAL
+
+
+def test_noalloc_solve_rejects_before_gpu_work():
+    """mg_solve_noalloc checks its arguments and the static array's size before any HIP call."""
+    lib = _lib.lib()
+    P = ctypes.c_void_p
+    g = grid(n=257, levels=8)  # 257^3 needs more than the static array holds
+    st = lib.mg_solve_noalloc(ctypes.byref(g), None, P(256), P(256), 1e-10, None, None, None)
+    assert st == _lib.MG_ENOMEM
+    assert "allocation-free" in _lib.last_error(None)
+    need = lib.mg_workspace_bytes(ctypes.byref(grid(n=129, levels=7)))
+    assert need <= _lib.NOALLOC_MAX_BYTES  # the largest constant-coefficient 3D grid it serves
+    g = grid(n=65, levels=6)
+    assert lib.mg_solve_noalloc(ctypes.byref(g), P(256), P(256), P(256), 1e-10, None, None,
+                                None) == MG_EINVAL  # k for a constant-coefficient grid
+    assert lib.mg_solve_noalloc(ctypes.byref(grid(n=65, levels=6, variable=1)), None, P(256),
+                                P(256), 1e-10, None, None, None) == MG_EINVAL
+    assert lib.mg_solve_noalloc(ctypes.byref(g), None, None, P(256), 1e-10, None, None,
+                                None) == MG_EINVAL
+    assert lib.mg_solve_noalloc(ctypes.byref(g), None, P(256), P(256), 0.0, None, None,
+                                None) == MG_EINVAL
+    assert lib.mg_solve_noalloc(None, None, P(256), P(256), 1e-10, None, None, None) == MG_EINVAL
