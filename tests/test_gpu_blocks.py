@@ -160,6 +160,50 @@ def test_transfers_match_oracle(B, order):
     rb.close()
 
 
+def test_row_tile_path_matches_oracle():
+    """From 64 cells per block on, the exchange, sweep and transfer kernels map a workgroup
+    to 64 x 4 cells of a plane instead of a flat cell range (the path of the 64^3 and 128^3
+    timings and of Table 1's larger sizes): one ghost exchange, one damped-Jacobi sweep, one
+    residual restriction and one prolongation at B = 64 with quadratic C2F against the
+    oracle."""
+    B, order = 64, 2
+    say(f"blocks row-tile path B={B} order={order}")
+    rng = np.random.default_rng(640)
+    rb = RefinedBlocks(B, order, device=DEV)
+    # exchange of random data
+    data = _random_level(rng, B)
+    ug = torch.from_numpy(data.copy()).to(DEV)
+    rb.fill(ug)
+    want = bl.fill(data.copy().reshape(-1), B, order).reshape(data.shape)
+    assert np.abs(host(ug) - want).max() <= 1e-13
+    del want
+    # one sweep with the harmonic Dirichlet data
+    u0, f = _start(B, rng)
+    ug = torch.from_numpy(u0.copy()).to(DEV)
+    fg = torch.from_numpy(f).to(DEV)
+    rb.jacobi(fg, ug, 1)
+    uo = bl.jacobi_sweep(u0.copy().reshape(-1), f.reshape(-1), B, order, g=bl.harmonic)
+    got = host(ug)[:, 1:-1, 1:-1, 1:-1]
+    want = uo.reshape(u0.shape)[:, 1:-1, 1:-1, 1:-1]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    del uo, got, want
+    # residual restriction onto 32 cells per block
+    u, f = _random_level(rng, B), _random_level(rng, B, -5.0, 5.0)
+    fc = rb.zeros(1)
+    rb.restrict_residual(0, torch.from_numpy(f).to(DEV), torch.from_numpy(u.copy()).to(DEV), fc)
+    want = bl.restrict(bl.residual(u.copy().reshape(-1), f.reshape(-1), B, order))
+    got = host(fc)[:, 1:-1, 1:-1, 1:-1]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    del got, want
+    # prolongation of a random correction
+    e, u2 = _random_level(rng, B // 2), _random_level(rng, B)
+    u2g = torch.from_numpy(u2.copy()).to(DEV)
+    rb.prolong_correct(0, torch.from_numpy(e.copy()).to(DEV), u2g)
+    want = bl.prolong_add(u2.copy().reshape(-1), e.copy().reshape(-1), B, order).reshape(u2.shape)
+    assert np.abs(host(u2g) - want).max() <= 1e-13 * np.abs(want).max()
+    rb.close()
+
+
 def test_coarse_level_smoothing_matches_oracle():
     B, order = 16, 2
     say("blocks coarse-level sweeps")

@@ -1,11 +1,13 @@
-"""GPU parity at the full 513^3 sizes, in the launch configuration bench.py times.
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times.
 
 Workload 3 (the benchmark): the oracle's FP64 V-cycle and FP64 solve at 513^3 against the
 GPU's, element by element; the FP32-refined solve against the oracle's FP64 solution.
 Workload 5 (variable coefficient, FP32 refinement in forward and adjoint): properties that
 hold at any size, evaluated by the oracle on the full grid (residuals of the GPU solutions),
 the fused gradient pass on seeded fields against the oracle's, autograd through the solve
-against the explicit adjoint, and a central difference of the loss.
+against the explicit adjoint, and central differences of the loss along k and f.
+Workload 4 (257^3, FP64): the adjoint gradient against central differences along smooth,
+single-node and right-hand-side directions, and against the oracle's own adjoint gradient.
 """
 import numpy as np
 import pytest
@@ -108,6 +110,95 @@ def test_workload5_fullsize_properties(oracle):
     an = float(torch.sum(dk * kd * vd))
     say(f"  dL/dk along v: fd={fd:.10e} adjoint={an:.10e}")
     assert abs(fd - an) <= 1e-6 * abs(an)
+
+    # and along a direction w of f (u is linear in f: the difference is exact up to rounding)
+    w = dev(inputs.uniform_interior(3, N, 57))
+    m = Multigrid(3, N, LEVELS, variable=True, max_cycles=40, device=DEV)
+    m.set_coefficients(kd)
+    up, _ = m.solve(fd_ + eps * w, tol=1e-30, raise_on_noconv=False)
+    um, _ = m.solve(fd_ - eps * w, tol=1e-30, raise_on_noconv=False)
+    m.close()
+    fdf = loss_difference(up, um, ud) / (2 * eps)
+    anf = float(torch.sum(df * w))
+    say(f"  dL/df along w: fd={fdf:.10e} adjoint={anf:.10e}")
+    assert abs(fdf - anf) <= 1e-6 * abs(anf)
+
+
+def loss_difference(up, um, uobs):
+    """L(up) - L(um) for L(u) = 0.5 ||u - uobs||^2, summed as 0.5 (up - um).(up + um - 2 uobs):
+    the difference of the two solutions is formed node by node, before the sum, so the sum's
+    rounding (relative to L itself) does not swamp a difference many orders smaller."""
+    return 0.5 * float(torch.sum((up - um) * (up + um - 2.0 * uobs)))
+
+
+def test_workload4_gradient_matches_fd_and_oracle(oracle):
+    """The differentiable workload at its own size (257^3, FP64, lognormal k, f = 1, u_obs from
+    the solve with the perturbed coefficient k_obs): the adjoint gradient against central
+    differences of fixed-cycle FP64 solves along a smooth Gaussian-random-field direction of
+    k, eight single nodes of k (one on the boundary: the gradient covers every node) and a
+    random direction of f, each within 1e-6; and against the oracle's adjoint gradient from
+    its own forward and adjoint solves."""
+    n, levels = 257, 8
+    say("workload 4 at 257^3: adjoint gradient vs finite differences and the oracle")
+    cfg = inputs.config(4)
+    k, f = cfg["k"], cfg["f"]
+    # u_obs: the oracle's solve with the perturbed coefficient, run to its rounding floor
+    uobs = np.zeros_like(f)
+    oracle.solve(f, uobs, levels, k=cfg["k_obs"], tol=1e-30, max_cycles=30, check=False)
+    kd, fd_, ud = dev(k), dev(f), dev(uobs)
+    mg = Multigrid(3, n, levels, variable=True, max_cycles=40, device=DEV)
+    mg.set_coefficients(kd)
+    # 40 cycles at a factor of about 0.26: down to the rounding floor
+    u, info = mg.solve(fd_, tol=1e-30, raise_on_noconv=False)
+    lam, _ = mg.solve_adjoint((u - ud).contiguous(), tol=1e-30, raise_on_noconv=False)
+    dk, df = mg.grad(u, lam)
+    say(f"  forward relres={info.relres:.3e} after {info.cycles} cycles")
+    assert oracle.rel_residual(f, host(u), k) <= 1e-10
+
+    def solve_fixed(kk, ff):
+        mg.set_coefficients(kk)
+        out, _ = mg.solve(ff, tol=1e-30, raise_on_noconv=False)
+        return out
+
+    def check_k(v, what):
+        vd = dev(v)
+        eps = 1e-4 / float(np.abs(v).max())
+        up = solve_fixed(kd * (1 + eps * vd), fd_)
+        um = solve_fixed(kd * (1 - eps * vd), fd_)
+        fd = loss_difference(up, um, ud) / (2 * eps)
+        an = float(torch.sum(dk * kd * vd))
+        say(f"  dL/dk along {what}: fd={fd:.10e} adjoint={an:.10e} rel={abs(fd - an) / abs(an):.1e}")
+        assert abs(fd - an) <= 1e-6 * abs(an)
+
+    check_k(inputs.gaussian_random_field(3, n, seed=41), "a smooth random field")
+    rng = np.random.default_rng(41)
+    nodes = [tuple(int(x) for x in rng.integers(1, n - 1, 3)) for _ in range(7)]
+    nodes.append((int(rng.integers(1, n - 1)), int(rng.integers(1, n - 1)), 0))  # boundary node
+    for node in nodes:
+        v = np.zeros((n, n, n))
+        v[node] = 1.0
+        check_k(v, f"node {node}")
+    w = inputs.uniform_interior(3, n, 42)
+    wd = dev(w)
+    eps = 1e-4
+    up = solve_fixed(kd, fd_ + eps * wd)
+    um = solve_fixed(kd, fd_ - eps * wd)
+    fdf = loss_difference(up, um, ud) / (2 * eps)
+    anf = float(torch.sum(df * wd))
+    say(f"  dL/df along a random field: fd={fdf:.10e} adjoint={anf:.10e}")
+    assert abs(fdf - anf) <= 1e-6 * abs(anf)
+    mg.close()
+
+    # the oracle's gradient from its own solves (same 40-cycle protocol as above; the
+    # oracle reaches its rounding floor within 30)
+    uo = np.zeros_like(f)
+    oracle.solve(f, uo, levels, k=k, tol=1e-30, max_cycles=30, check=False)
+    lo = np.zeros_like(f)
+    oracle.solve(uo - uobs, lo, levels, k=k, tol=1e-30, max_cycles=30, check=False)
+    dk_or, df_or = oracle.grad(uo, lo)
+    ek, ef = relmax(host(dk), dk_or), relmax(host(df), df_or)
+    say(f"  vs oracle gradient: dk {ek:.2e}, df {ef:.2e}")
+    assert ek <= 1e-9 and ef <= 1e-9
 
 
 def test_gradient_pass_fullsize_matches_oracle(oracle):

@@ -55,6 +55,28 @@ def test_stencils_match_oracle(n, levels):
     mg.close()
 
 
+@pytest.mark.parametrize("n,levels,upto", [(129, 7, 6), (257, 8, 1)])
+def test_stencils_match_oracle_on_streamed_fine_levels(n, levels, upto):
+    """From a 129^3 fine level on, the first coarse stencil is built with the streaming
+    (temporally blocked) fine-level kernels: levels 1..upto against the oracle's sparse
+    products, at 129^3 (every level) and at 257^3 (the first coarse level of the 257^3
+    workload; the level the 513^3 workload builds the same way from 513^3)."""
+    say(f"galerkin stencils on the streamed path n={n} levels 1..{upto}")
+    k = inputs.lognormal_k(3, n, seed=4)
+    mg = GalerkinMultigrid(to_gpu(k), levels)
+    A = g.hierarchy(k, upto + 1)
+    nl = n
+    for l in range(1, upto + 1):
+        nl = (nl - 1) // 2 + 1
+        want = stencil_arrays(A[l], nl)
+        got = mg.stencil(l).cpu().numpy()
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say(f"  level {l} ({nl}^3): max error {err:.2e} of the largest entry")
+        assert err <= 1e-12, l
+        del want, got
+    mg.close()
+
+
 @pytest.mark.parametrize("nu", [(2, 2), (1, 3)])
 def test_vcycles_match_oracle(nu):
     n, levels = 33, 5
