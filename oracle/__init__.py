@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
             "or_interior_norm2": (d, [i, i, P]),
             "or_vcycle": (i, [i, i, i, i, i, P, P, P]),
             "or_solve": (i, [i, i, i, i, i, i, i, P, P, P, d, P, P, P]),
+            "or_last_solve_seconds": (d, []),
             "or_grad": (None, [i, i, P, P, P, P]),
             "or_fv_apply": (None, [i, d, P, P]),
             "or_fv_residual": (None, [i, d, P, P, P]),
@@ -231,6 +232,12 @@ def solve(f, u, levels, k=None, tol=1e-10, nu1=2, nu2=2, max_cycles=100,
     if check and st not in (0,):
         raise RuntimeError(f"solve: {STATUS.get(st, st)}")
     return cyc.value, rel.value, hist[: cyc.value + 1].copy(), st
+
+
+def last_solve_seconds():
+    """Wall time of the last solve() from its first norm to its last cycle (the hierarchy's
+    allocation and release excluded)."""
+    return float(lib().or_last_solve_seconds())
 
 
 def grad(u, lam):
