@@ -109,6 +109,78 @@ def pmc_sample(n: int):
     print("pmc sample done", file=sys.stderr)
 
 
+def pmc_ir_sample(n: int):
+    """Counter-run workload for the kernels of the FP32-refined solve: the calibration copy,
+    then two FP32-refined solves of the benchmark workload."""
+    import torch
+
+    from paper_2403_08063_amd import Multigrid, inputs
+
+    dev = torch.device("cuda:0")
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    levels = (n - 1).bit_length() - 1
+    f = torch.from_numpy(inputs.uniform_interior(3, n, seed=3)).to(dev)
+    mg = Multigrid(3, n, levels, precision="f32_ir", device=dev)
+    for _ in range(2):
+        mg.solve(f, tol=1e-10)
+    torch.cuda.synchronize()
+    print("pmc ir sample done", file=sys.stderr)
+
+
+# Algorithmic bytes per interior node of the fine-level kernels of the FP32-refined solve,
+# by kernel-name pattern: (pattern, what it is, bytes per node)
+IR_KERNELS = [
+    ("k_rbgs_tiled<float, false, 2, 8, 6, 2, 1, 1", "FP32 pre-smoothing from 0 + residual restriction",
+     4 + 4 + 0.5),
+    ("k_rbgs_tiled<float, false, 2, 12, 4, 2, 2, 0", "FP32 post-smoothing with the prolongation",
+     4 + 4 + 4 + 0.5),
+    ("k_pass<false, 2,", "refinement pass (u += s e, r = f - A u, norm, r32)", 8 + 8 + 4 + 8 + 4),
+    ("k_pass<false, 6,", "first refinement pass (+ right-hand-side norm)", 8 + 8 + 8 + 4),
+]
+
+
+def summarize_pmc_kernels(fetch_dir: str, write_dir: str, n: int):
+    """Per-dispatch HBM bytes of the fine-level launches (the largest dispatches of each
+    kernel) of the FP32-refined solve, from the two counter runs of pmc_ir_sample, each
+    counter scaled so that the calibration copy reads exactly its known size; a markdown
+    table on stdout."""
+    import csv
+    import glob
+
+    meas = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r.get("Counter_Name") == counter:
+                    rows.append((_short_kernel_name(r["Kernel_Name"]), float(r["Counter_Value"])))
+        copy = [v for name, v in rows if "copy" in name.lower() and "fill" not in name.lower()]
+        if not copy:
+            raise SystemExit(f"{counter}: no calibration copy in {d}")
+        factor = (CALIB_BYTES / 1024.0) / copy[0]
+        for pat, _, _ in IR_KERNELS:
+            vals = [v for name, v in rows if name.startswith(pat)]
+            if not vals:
+                continue
+            top = max(vals)
+            fine = [v for v in vals if v >= 0.5 * top]  # the fine-level dispatches
+            meas.setdefault(pat, {})[key] = (sum(fine) / len(fine) * 1024.0 * factor, len(fine), factor)
+    m = (n - 2) ** 3
+    print(f"| kernel | what | fine-level dispatches | FETCH bytes | WRITE bytes | measured / algorithmic |")
+    print("|---|---|---:|---:|---:|---:|")
+    for pat, what, bpn in IR_KERNELS:
+        if pat not in meas or len(meas[pat]) < 2:
+            continue
+        fb, cnt, _ = meas[pat]["fetch"]
+        wb, _, _ = meas[pat]["write"]
+        print(f"| `{pat}...>` | {what} | {cnt} | {fb:.3e} | {wb:.3e} | "
+              f"{(fb + wb) / (bpn * m):.3f} ({bpn:g} B per node) |")
+
+
 def pmc_fv_sample(N: int = 512):
     """Counter-run workload for the paper's FV sweep: the calibration copy, then 10 damped
     Jacobi sweeps on the 512^3-cell level (the exact-partition pass)."""
@@ -699,6 +771,10 @@ def main():
                     help="run only the paper-benchmark (cell-centred FV) leg, print its record")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--pmc-ir-sample", action="store_true",
+                    help="counter-run workload: calibration copy + 2 FP32-refined solves at n")
+    ap.add_argument("--summarize-pmc-kernels", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="per-kernel HBM traffic of the FP32-refined solve's fine level")
     ap.add_argument("--pmc-fv-sample", action="store_true",
                     help="counter-run workload: calibration copy + 10 FV Jacobi sweeps at 512^3")
     ap.add_argument("--summarize-pmc-fv", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -717,6 +793,12 @@ def main():
         return
     if args.pmc_fv_sample:
         pmc_fv_sample()
+        return
+    if args.pmc_ir_sample:
+        pmc_ir_sample(args.n)
+        return
+    if args.summarize_pmc_kernels:
+        summarize_pmc_kernels(*args.summarize_pmc_kernels, args.n)
         return
     if args.summarize_pmc_fv:
         summarize_pmc_fv(*args.summarize_pmc_fv)

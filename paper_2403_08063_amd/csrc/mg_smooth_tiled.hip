@@ -56,13 +56,25 @@ constexpr int imod(int a, int m) { return ((a % m) + m) % m; }
 // final: two more queued planes, a 4-node wider tile overlap in x and y (the residual is
 // exact one node, its full weighting two nodes further inside than the final values) and
 // 2 more final planes at each end of the z-chunk.
-template <typename T, bool VAR, int S, int W, int RPW, int PD, int RES = 0>
+//
+// LW = lanes per tile row: 64 (a wave's lanes span the tile's 128 columns), or 32 (the tile
+// is 64 columns wide and each wave holds two row bands of RPW rows, lanes 0-31 the first and
+// lanes 32-63 the second: a squarer tile of the same node count, with less halo per output
+// node).  A band of 32 lanes is then a "row group" of its own: it exchanges edge rows with
+// the neighbouring groups through LDS like a wave does, and its x-neighbours come from the
+// adjacent lanes by the same wave-wide shift -- lane 32's left neighbour is lane 31 of the
+// other band, a value of another row, but column 0 of a tile is never exact (nor is column
+// 63, which receives lane 32's value), so no exact value reads it.
+template <typename T, bool VAR, int S, int W, int RPW, int PD, int RES = 0, int LW = 64>
 struct Tiled {
   static_assert(PD == 1 || PD == 2, "prefetch depth");
   static_assert(RES == 0 || (!VAR && S == 2), "the fused restriction serves the plain 2-sweep pass");
+  static_assert(LW == 64 || LW == 32, "lanes per tile row");
+  static constexpr int G = 64 / LW;      // row groups per wave
+  static constexpr int VW = W * G;       // row groups per tile
   static constexpr int H = 2 * S;        // halo = number of stages
-  static constexpr int BX = 128;         // columns per tile (2 per lane)
-  static constexpr int BY = W * RPW;     // rows per tile
+  static constexpr int BX = 2 * LW;      // columns per tile (2 per lane)
+  static constexpr int BY = VW * RPW;    // rows per tile
   static constexpr int XR = RES ? 4 : 0; // extra overlap for the fused restriction
   static constexpr int ZR = RES ? 2 : 0; // extra final planes at each end of a z-chunk
   static constexpr int TXO = BX - 2 * H - XR; // output columns per tile (tile stride)
@@ -72,13 +84,13 @@ struct Tiled {
   static_assert(TYO > 0, "tile too short for the halo");
 
   struct Shared {
-    T eu[2][H][W][2][64];                    // wave-boundary rows of u
-    T ek[VAR ? 2 : 1][VAR ? H : 1][W][2][64]; // and of k
-    T er[RES ? 2 : 1][RES ? W : 1][2][2][64]; // RES: both columns of a final plane's edge rows
-    T erx[RES ? 2 : 1][RES ? W : 1][64];      // RES: x-filtered residual of a wave's first row
+    T eu[2][H][VW][2][LW];                     // row-group boundary rows of u
+    T ek[VAR ? 2 : 1][VAR ? H : 1][VW][2][LW]; // and of k
+    T er[RES ? 2 : 1][RES ? VW : 1][2][2][LW]; // RES: both columns of a final plane's edge rows
+    T erx[RES ? 2 : 1][RES ? VW : 1][LW];      // RES: x-filtered residual of a group's first row
   };
 
-  // The first column of every lane and the first row of every wave have odd global
+  // The first column of every lane and the first row of every row group have odd global
   // indices (tile origins are odd, H and RPW even): the fused prolongation relies on it.
   static_assert(TXO % 2 == 0 && TYO % 2 == 0 && H % 2 == 0, "odd tile origins");
 
@@ -93,23 +105,25 @@ struct Tiled {
                                              int n, T h2, int ox, int oy, int z0, int z1,
                                              T ih2, T* __restrict__ fc, Shared& sh)
   {
-    const int lane = threadIdx.x & 63;
-    // wave index, made explicitly wave-uniform so that row bookkeeping stays scalar
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // lane within its row group, and the row group (wave-uniform for LW = 64, so that row
+    // bookkeeping stays scalar there)
+    const int lane = threadIdx.x & (LW - 1);
+    const int w = LW == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)
+                           : (int)(threadIdx.x >> 5);
     const int gxa = ox - H + 2 * lane;  // global x of this lane's first column
-    const int gyw = oy - H + w * RPW;   // global y of this wave's first row
-    const int wm = w > 0 ? w - 1 : 0, wp = w < W - 1 ? w + 1 : W - 1;  // adjacent waves
+    const int gyw = oy - H + w * RPW;   // global y of this row group's first row
+    const int wm = w > 0 ? w - 1 : 0, wp = w < VW - 1 ? w + 1 : VW - 1;  // adjacent groups
 
-    // Addresses: a wave-uniform plane + row base (scalar registers) plus a per-lane 32-bit
-    // column byte offset.  Coordinates outside the grid are clamped onto it, so every load
-    // is in bounds; such positions are never updated and never read by an exact value.
-    // Bit 2i+o of `upd` (per lane): node (row i, column o) is interior to the grid and
-    // may be updated.  Stores go to output rows (`rowout`, uniform) at the column offset
-    // `sxb`, which is out of the plane's range -- the store is dropped -- for columns that
-    // are not output columns of this tile.
+    // Addresses: a wave-uniform plane + row base (scalar registers; per lane for LW = 32)
+    // plus a per-lane 32-bit column byte offset.  Coordinates outside the grid are clamped
+    // onto it, so every load is in bounds; such positions are never updated and never read
+    // by an exact value.  Bit 2i+o of `upd` (per lane): node (row i, column o) is interior
+    // to the grid and may be updated.  Stores go to output rows (`rowout`) at the column
+    // offset `sxb`, which is out of the plane's range -- the store is dropped -- for columns
+    // that are not output columns of this tile.
     uint32_t cxb[2], sxb[2];
     unsigned upd = 0, rowout = 0;
-    uint32_t rowb[RPW];  // clamped row start within a plane, in bytes (uniform)
+    uint32_t rowb[RPW];  // clamped row start within a plane, in bytes
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
       const int gx = gxa + o, px = 2 * lane + o;
@@ -130,6 +144,13 @@ struct Tiled {
       rowb[i] = (uint32_t)(min(max(gy, 0), n - 1) * n) * (uint32_t)sizeof(T);
     }
     const uint32_t planeb = (uint32_t)((size_t)n * (size_t)n * sizeof(T));
+    // Plane accesses at (row offset ro, column offset co): the row offset is the scalar
+    // operand for LW = 64 and joins the per-lane offset for LW = 32.  Out-of-range column
+    // offsets stay out of range.
+    auto ld = [](PlaneBuf b, uint32_t co, uint32_t ro) -> T {
+      if constexpr (LW == 64) return buf_load<T>(b, co, ro);
+      else return buf_load<T>(b, co + ro, 0u);
+    };
 
     T U[Q][RPW][2], F[Q][RPW][2], K[Q][RPW][2];
     // Prefetch buffers: plane zl+PD is loaded in the step that inserts plane zl, so each
@@ -154,7 +175,7 @@ struct Tiled {
     // (Byte offsets: coarse rows uniform, coarse columns per lane.)
     constexpr int CR = RPW / 2 + 1;
     T CA[PD][CR][2], CB[PD][CR][2];
-    uint32_t ccb[2] = {0, 0}, crb[CR];
+    uint32_t ccb[2] = {0, 0}, crb[CR];  // crb: uniform for LW = 64
     const uint32_t cplaneb = (uint32_t)((size_t)nc * (size_t)nc * sizeof(T));
     if (IN == kInProlong) {
       const int cxa = (gxa - 1) >> 1;
@@ -170,7 +191,7 @@ struct Tiled {
 #pragma unroll
       for (int r = 0; r < CR; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) E[r][c] = buf_load<T>(be, ccb[c], crb[r]);
+        for (int c = 0; c < 2; ++c) E[r][c] = ld(be, ccb[c], crb[r]);
     };
 
     // Loads of plane zl (parity ZP, known at compile time: see the step below) into
@@ -190,9 +211,9 @@ struct Tiled {
       for (int i = 0; i < RPW; ++i) {
 #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          PU[bf_][i][o] = IN == kInZero ? T(0) : buf_load<T>(bu, cxb[o], rowb[i]);
-          PF[bf_][i][o] = buf_load<T>(bf, cxb[o], rowb[i]);
-          if constexpr (VAR) PK[bf_][i][o] = buf_load<T>(bk, cxb[o], rowb[i]);
+          PU[bf_][i][o] = IN == kInZero ? T(0) : ld(bu, cxb[o], rowb[i]);
+          PF[bf_][i][o] = ld(bf, cxb[o], rowb[i]);
+          if constexpr (VAR) PK[bf_][i][o] = ld(bk, cxb[o], rowb[i]);
         }
       }
     };
@@ -248,9 +269,18 @@ struct Tiled {
       const PlaneBuf bo = plane_buf(uout, (size_t)pout * planeb, planeb);
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        if (!((rowout >> i) & 1u)) continue;
+        if constexpr (LW == 64) {
+          if (!((rowout >> i) & 1u)) continue;
 #pragma unroll
-        for (int o = 0; o < 2; ++o) buf_store(U[so][i][o], bo, sxb[o], rowb[i]);
+          for (int o = 0; o < 2; ++o) buf_store(U[so][i][o], bo, sxb[o], rowb[i]);
+        } else {
+          // per-lane rows: a row that is not an output row takes the out-of-range offset
+          const bool ro = (rowout >> i) & 1u;
+#pragma unroll
+          for (int o = 0; o < 2; ++o)
+            buf_store(U[so][i][o], bo,
+                      (ro && sxb[o] != 0x80000000u) ? sxb[o] + rowb[i] : 0x80000000u, 0u);
+        }
       }
     };
 
@@ -471,13 +501,13 @@ struct Tiled {
   }
 };
 
-template <typename T, bool VAR, int S, int W, int RPW, int PD, int IN, int RES>
+template <typename T, bool VAR, int S, int W, int RPW, int PD, int IN, int RES, int LW>
 __global__ void __launch_bounds__(64 * W)
     k_rbgs_tiled(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
                  const T* __restrict__ k, const T* __restrict__ ec, int nc, int n, T h2,
                  T ih2, T* __restrict__ fc, int tiles_x, int tiles_y, int zlen)
 {
-  using C = Tiled<T, VAR, S, W, RPW, PD, RES>;
+  using C = Tiled<T, VAR, S, W, RPW, PD, RES, LW>;
   __shared__ typename C::Shared sh;
   // XCD-aware tile index: workgroup b runs on XCD b % 8; XCD x gets tiles
   // [start_x, start_x + count_x) in order.
@@ -491,7 +521,7 @@ __global__ void __launch_bounds__(64 * W)
   const int z0 = 1 + tz * zlen;
   const int z1 = min(z0 + zlen, n - 1);
   // parity of (x of column 0) + (y of row 0) + z0 - 1; RPW is even, so it is the same
-  // for every wave's first row
+  // for every row group's first row
   const int b0 = ((ox - C::H) + (oy - C::H) + z0 - 1) & 1;
   if (b0) C::template run<1, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, sh);
   else C::template run<0, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, sh);
@@ -499,6 +529,7 @@ __global__ void __launch_bounds__(64 * W)
 
 struct LaunchShape {
   int tiles_x, tiles_y, nchunks, zlen, blocks;
+  long long cost;  // rounds of resident workgroups x planes per workgroup
 };
 
 // Workgroups of this kernel that fit on the device at once (CUs x resident per CU),
@@ -548,6 +579,7 @@ LaunchShape shape_for(int n, int capacity)
   }
   L.nchunks = (m + L.zlen - 1) / L.zlen;
   L.blocks = per * L.nchunks;
+  L.cost = best;
   return L;
 }
 
@@ -595,6 +627,12 @@ LaunchShape shape_for(int n, int capacity)
 #ifndef MG_SMOOTH32_RES_PD
 #define MG_SMOOTH32_RES_PD 2
 #endif
+#ifndef MG_SMOOTH32_RES_NARROW
+#define MG_SMOOTH32_RES_NARROW 0
+#endif
+#ifndef MG_SMOOTH32_PROLONG_NARROW
+#define MG_SMOOTH32_PROLONG_NARROW 0
+#endif
 template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
@@ -613,22 +651,40 @@ struct Shape {
                             : IN == kInProlong ? (f32 ? MG_SMOOTH32_PROLONG_PD : 1)
                             : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
                                                : (f32 ? MG_SMOOTH32_READ_PD : 1);
+  // whether the 64-column layout (LW = 32) is compiled for this pass: its per-lane row
+  // offsets cost ~20-30 VGPRs, which the FP64 variable-coefficient pass does not have to
+  // spare (it would spill)
+  static constexpr bool NARROW = RES ? MG_SMOOTH32_RES_NARROW
+                                 : IN == kInProlong ? MG_SMOOTH32_PROLONG_NARROW
+                                                    : !(VAR && !f32);
 };
 
+// The two tile layouts of a pass (128 columns x W*RPW rows, or 64 columns x 2*W*RPW rows)
+// hold the same nodes per workgroup; the one whose launch shape costs fewer planes per
+// workgroup on the critical path at this grid size is launched (the 128-column layout on
+// a tie).  Both give bitwise the same result.
 template <typename T, bool VAR, int S, int IN, int RES = 0>
 void launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
                const T* ec, T* fc = nullptr)
 {
   using Sh = Shape<T, VAR, S, IN, RES>;
   constexpr int W = Sh::W, RPW = Sh::RPW, PD = Sh::PD;
-  using C = Tiled<T, VAR, S, W, RPW, PD, RES>;
-  auto kern = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN, RES>;
-  const LaunchShape L = shape_for<C>(n, resident_capacity(kern, 64 * W));
   const T h2 = (T)(h * h);
   const int nc = (n - 1) / 2 + 1;
   const T ih2 = (T)(1.0 / (h * h));
-  kern<<<L.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, ih2, fc, L.tiles_x, L.tiles_y,
-                                   L.zlen);
+  auto k64 = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN, RES, 64>;
+  const LaunchShape L64 = shape_for<Tiled<T, VAR, S, W, RPW, PD, RES, 64>>(n, resident_capacity(k64, 64 * W));
+  if constexpr (Sh::NARROW) {
+    auto k32 = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN, RES, 32>;
+    const LaunchShape L32 = shape_for<Tiled<T, VAR, S, W, RPW, PD, RES, 32>>(n, resident_capacity(k32, 64 * W));
+    if (L32.cost < L64.cost) {
+      k32<<<L32.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, ih2, fc, L32.tiles_x,
+                                        L32.tiles_y, L32.zlen);
+      return;
+    }
+  }
+  k64<<<L64.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, ih2, fc, L64.tiles_x,
+                                    L64.tiles_y, L64.zlen);
 }
 
 template <typename T, bool VAR, int S>
