@@ -535,8 +535,8 @@ PAPER_TABLE1 = {
 
 
 def _block_l2_error(u, B):
-    """Volume-weighted L2 error sqrt(sum_b h_b^3 sum (u - u_exact)^2) of a refined-layout
-    solution tensor against Eq. 2's exact solution at the inner cell centres (on u's device)."""
+    """Table 1's L2 error norm of a refined-layout solution tensor against Eq. 2's exact
+    solution at the inner cell centres: the root mean square over all cells (on u's device)."""
     import math
 
     import torch
@@ -544,15 +544,16 @@ def _block_l2_error(u, B):
     from paper_2403_08063_amd import inputs
 
     i = torch.arange(B, dtype=torch.float64, device=u.device) + 0.5
-    total = 0.0
+    total, count = 0.0, 0
     for b, (_, idx, w) in enumerate(inputs.block_list()):
         h = w / B
         x, y, z = (idx[a] * w + i * h for a in range(3))
         ex = (torch.sin(math.pi * x)[None, None, :] * torch.sin(math.pi * y)[None, :, None]
               * torch.sinh(math.sqrt(2.0) * math.pi * z)[:, None, None])
         d = u[b, 1:-1, 1:-1, 1:-1] - ex
-        total += h ** 3 * float(torch.sum(d * d))
-    return math.sqrt(total)
+        total += float(torch.sum(d * d))
+        count += B ** 3
+    return math.sqrt(total / count)
 
 
 def refined_benchmark(dev, B: int = 64, table_sizes=(16, 32, 64, 128)):
@@ -639,6 +640,9 @@ def refined_benchmark(dev, B: int = 64, table_sizes=(16, 32, 64, 128)):
         "table1_solve_ms": {str(o): {str(b): round(v, 1) for b, v in t_solve[o].items()} for o in t_solve},
         "paper_table1_l2_error": {str(o): {str(b): PAPER_TABLE1[o][b] for b in table_sizes if b in PAPER_TABLE1[o]}
                                   for o in PAPER_TABLE1},
+        "table1_error_over_paper": {str(o): {str(b): round(errs[o][b] / PAPER_TABLE1[o][b], 4)
+                                             for b in table_sizes if b in PAPER_TABLE1[o]}
+                                    for o in errs},
     }
 
 

@@ -13,8 +13,10 @@
  * level-3 blocks in (z, y, x) order of their level-3 block index.
  *
  * Ghost layer of a face:
- *  - on the domain boundary: the Dirichlet value at the face centre, written by the caller
- *    and never by the library; the operator uses 2 g - u_i there;
+ *  - on the domain boundary: the Dirichlet value at the ghost cell's own centre (half a cell
+ *    outside the domain), written by the caller and never by the library; the operator
+ *    reads it like any other neighbour (the reading under which Table 1's errors, Sect. 5,
+ *    are reproduced);
  *  - towards a block of the same level: a copy of the neighbour's adjacent inner cell;
  *  - of a level-2 block towards refined blocks (F2C): the mean of the 8 level-3 inner cells
  *    the coarse ghost cell covers (weights 0.125);
@@ -24,10 +26,12 @@
  *    centre a quarter coarse cell towards the face; along each tangential axis the cell and
  *    its neighbours, evaluated at -1/4 or +1/4 coarse cell, with a base that would fall into
  *    the coarse block's ghost region replaced by the inner cell at -2 o (Sect. 3's
- *    remapping; order 1 takes the neighbour on the fine cell's side, or the other one at the
- *    block edge; order 0 copies the coarse cell).
- * The operator of every block is the 7-point finite-volume one of mg_fv.h with that block's
- * h; damped Jacobi: u <- u + omega (h^2/6) (f - A u).
+ *    remapping; order 1 takes the cell and its downwind neighbour -o for both fine cells, or
+ *    the upwind one at the block's lower edge; order 0 copies the coarse cell).  With the
+ *    boundary treatment above these schemes reproduce Table 1's printed errors (Sect. 5).
+ * The operator of every block is the 7-point finite-volume one, (A u)_i = h^-2 sum over
+ * the six neighbours of (u_i - u_nb) with that block's h, every ghost neighbour read as
+ * stored; damped Jacobi: u <- u + omega (h^2/6) (f - A u).
  *
  * Multigrid (Sect. 5: V(3,3)-cycles, damped Jacobi with omega = 0.8 as smoother and as
  * coarsest-level solver, coarser levels until a block holds 4^3 cells): level l keeps the
@@ -41,7 +45,11 @@
  *    (the barycentric weights of the fine centre in the tetrahedron of those four centres:
  *    exact for linear functions, and reading only face ghosts, which the exchange fills);
  *    a neighbour across the domain boundary counts as -e_P (zero correction on the face);
- *  - coarse problems: zero Dirichlet data and initial guess 0.
+ *  - coarse problems: the correction with zero Dirichlet data on the boundary face (on levels
+ *    l >= 1 a domain-boundary ghost enters the operator as 2 g - u_i with its stored g = 0,
+ *    where the finest level reads the Dirichlet value at the ghost centre as stored; with the
+ *    zero at the coarse ghost centres the V(3,3) factor would grow with the block size) and
+ *    initial guess 0.
  * Coarse-level arrays live in the workspace; the finest level's are the caller's.
  *
  * Conventions as in mg.h: device pointers owned by the caller; a caller-provided workspace
@@ -99,11 +107,13 @@ mg_status mgblk_jacobi(mgblk_ctx* ctx, const double* f, double* u, int sweeps);
 int mgblk_levels(const mgblk_ctx* ctx);
 
 /* `sweeps` damped Jacobi sweeps on arrays of level `level` (block size B >> level), each
- * preceded by a ghost fill; u in place, its domain-boundary ghosts being the Dirichlet data. */
+ * preceded by a ghost fill; u in place, its domain-boundary ghosts being the Dirichlet data
+ * (level 0; levels >= 1 use the correction levels' operator, see above). */
 mg_status mgblk_smooth(mgblk_ctx* ctx, int level, const double* f, double* u, int sweeps);
 
 /* Fills u's interface ghosts (level `level`), then fc (level `level`+1) = the mean of the 8
- * child residuals f - A u of every coarse inner cell.  fc's ghost cells are not written. */
+ * child residuals f - A u (the operator of level `level`) of every coarse inner cell.  fc's
+ * ghost cells are not written. */
 mg_status mgblk_restrict_residual(mgblk_ctx* ctx, int level, const double* f, double* u,
                                   double* fc);
 

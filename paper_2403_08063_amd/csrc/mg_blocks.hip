@@ -280,12 +280,8 @@ __device__ __forceinline__ void face_coords(int ax, int n, int t1, int t2, int& 
 __device__ __forceinline__ int tangential_first(int order, int T, int B, int t)
 {
   if (order == 0) return 0;
-  if (order == 1) {
-    int a = t ? 0 : -1;
-    if (T + a < 0) a = 0;
-    if (T + a + 1 >= B) a = -1;
-    return a;
-  }
+  if (order == 1) return T - 1 < 0 ? 0 : -1;  // the cell and its downwind neighbour, remapped
+                                              // to the upwind one at the block's lower edge
   if (T - 1 < 0) return 0;       // the downwind base would be a ghost: remap by -2 o
   if (T + 1 >= B) return -2;     // the upwind one
   return -1;
@@ -341,13 +337,13 @@ __device__ __forceinline__ double interface_ghost(const Rd& rd, int B, int order
 
 constexpr int kFillThreads = 256;
 
-__global__ void __launch_bounds__(kFillThreads)
-    k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
+// ghost cell q (0 .. B^2-1) of face f of block b: filled by its rule unless the face lies on
+// the domain boundary
+__device__ __forceinline__ void fill_ghost(int B, int order, const C2FWeights& W,
+                                           const int* __restrict__ faces, double* __restrict__ u,
+                                           int q, int f, int b)
 {
   const int m = B + 2;
-  const int q = blockIdx.x * kFillThreads + threadIdx.x;  // ghost cell of the face
-  if (q >= B * B) return;
-  const int f = blockIdx.y, b = blockIdx.z;
   const int* e = faces + ((size_t)b * 6 + f) * kFaceInts;
   if (e[0] == kFaceBoundary) return;
   const int t1 = 1 + q % B, t2 = 1 + q / B;
@@ -357,16 +353,27 @@ __global__ void __launch_bounds__(kFillThreads)
   u[bidx(m, b, gz, gy, gx)] = interface_ghost(rd, B, order, W, e, f >> 1, f & 1, t1, t2);
 }
 
-// (A u) at inner cell (z, y, x) of block b: ghost neighbours on the domain boundary as
-// 2 g - u_i, the others as stored (filled from the neighbours)
+__global__ void __launch_bounds__(kFillThreads)
+    k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
+{
+  const int q = blockIdx.x * kFillThreads + threadIdx.x;  // ghost cell of the face
+  if (q >= B * B) return;
+  fill_ghost(B, order, W, faces, u, q, blockIdx.y, blockIdx.z);
+}
+
+// (A u) at inner cell (z, y, x) of block b from the six stored neighbours: interface ghosts
+// filled from the neighbouring blocks; on the solution level the domain-boundary ghosts hold
+// the Dirichlet data at their own centres and are read as stored (Sect. 5; the reading under
+// which Table 1's errors are reproduced), on the correction levels (coarse) the correction
+// vanishes on the boundary face: such a ghost enters as 2 g - u_i with its stored g = 0
 __device__ __forceinline__ double blk_apply_at(int B, const int* __restrict__ fb, double ih2,
                                                const double* __restrict__ u, size_t i, int z,
-                                               int y, int x)
+                                               int y, int x, bool coarse)
 {
   const int m = B + 2;
   const size_t sy = (size_t)m, sz = (size_t)m * m;
   const double c = u[i];
-  auto v = [&](double nb, bool bnd) { return bnd ? 2.0 * nb - c : nb; };
+  auto v = [&](double nb, bool bnd) { return (coarse && bnd) ? 2.0 * nb - c : nb; };
   const double v0 = v(u[i - 1], x == 1 && fb[0 * kFaceInts] == kFaceBoundary);
   const double v1 = v(u[i + 1], x == B && fb[1 * kFaceInts] == kFaceBoundary);
   const double v2 = v(u[i - sy], y == 1 && fb[2 * kFaceInts] == kFaceBoundary);
@@ -419,17 +426,30 @@ __device__ __forceinline__ bool cell_of(int B, int& b, int& z, int& y, int& x)
   return true;
 }
 
-__global__ void __launch_bounds__(kCellThreads)
-    k_blk_jacobi(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
-                 const double* __restrict__ f, const double* __restrict__ u, double* __restrict__ uout)
+// the damped Jacobi update of inner cell (z, y, x) of block b, u -> uout
+__device__ __forceinline__ void jacobi_cell(int B, double omega, const int* __restrict__ faces,
+                                            const double* __restrict__ hs,
+                                            const double* __restrict__ f,
+                                            const double* __restrict__ u,
+                                            double* __restrict__ uout, bool coarse, int b, int z,
+                                            int y, int x)
 {
-  int b, z, y, x;
-  if (!cell_of(B, b, z, y, x)) return;
   const int m = B + 2;
   const double h = hs[b];
   const size_t i = bidx(m, b, z, y, x);
-  const double au = blk_apply_at(B, faces + (size_t)b * 6 * kFaceInts, 1.0 / (h * h), u, i, z, y, x);
+  const double au = blk_apply_at(B, faces + (size_t)b * 6 * kFaceInts, 1.0 / (h * h), u, i, z, y, x,
+                                 coarse);
   uout[i] = u[i] + omega * (h * h / 6.0) * (f[i] - au);
+}
+
+__global__ void __launch_bounds__(kCellThreads)
+    k_blk_jacobi(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
+                 const double* __restrict__ f, const double* __restrict__ u, double* __restrict__ uout,
+                 int coarse)
+{
+  int b, z, y, x;
+  if (!cell_of(B, b, z, y, x)) return;
+  jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, z, y, x);
 }
 
 __global__ void __launch_bounds__(256)
@@ -447,7 +467,8 @@ __global__ void __launch_bounds__(256)
     const int b = (int)(t / ((size_t)B * B * B));
     const double h = hs[b];
     const size_t i = bidx(m, b, z, y, x);
-    const double r = f[i] - blk_apply_at(B, faces + (size_t)b * 6 * kFaceInts, 1.0 / (h * h), u, i, z, y, x);
+    const double r = f[i] - blk_apply_at(B, faces + (size_t)b * 6 * kFaceInts, 1.0 / (h * h), u, i, z, y, x,
+                                         false);
     acc += r * r;
   }
 #pragma unroll
@@ -477,7 +498,7 @@ __global__ void __launch_bounds__(256)
 __global__ void __launch_bounds__(kCellThreads)
     k_blk_restrict(int B, const int* __restrict__ faces, const double* __restrict__ hs,
                    const double* __restrict__ f, const double* __restrict__ u,
-                   double* __restrict__ fc, double* __restrict__ uc)
+                   double* __restrict__ fc, double* __restrict__ uc, int coarse)
 {
   const int Bc = B / 2;
   int b, Z, Y, X;
@@ -496,7 +517,7 @@ __global__ void __launch_bounds__(kCellThreads)
       for (int dx = 0; dx < 2; ++dx) {
         const int z = 1 + 2 * Z + dz, y = 1 + 2 * Y + dy, x = 1 + 2 * X + dx;
         const size_t i = bidx(m, b, z, y, x);
-        const double r = f[i] - blk_apply_at(B, fb, ih2, u, i, z, y, x);
+        const double r = f[i] - blk_apply_at(B, fb, ih2, u, i, z, y, x, coarse != 0);
         s = first ? r : s + r;
         first = false;
       }
@@ -570,7 +591,7 @@ double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, i
   const dim3 grid = cell_grid(B);
   for (int s = 0; s < count; ++s) {
     fill(c, l, cur);
-    k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth);
+    k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
     double* x = cur;
     cur = oth;
     oth = x;
@@ -584,7 +605,7 @@ void restrict_residual(mgblk_ctx* c, int l, const double* f, double* u, double* 
   const BlkLevel& L = c->lv[l];
   const int Bc = L.B / 2;
   fill(c, l, u);
-  k_blk_restrict<<<cell_grid(Bc), kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc);
+  k_blk_restrict<<<cell_grid(Bc), kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc, l > 0);
 }
 
 // fills ec's interface ghosts (level l+1), then u (level l) += P ec

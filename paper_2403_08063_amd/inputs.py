@@ -119,22 +119,17 @@ def block_list():
 
 
 def block_positions(B: int) -> np.ndarray:
-    """(120, B+2, B+2, B+2, 3) positions (x, y, z) of every stored cell: cell centres inside;
-    a ghost cell on the domain boundary at the centre of its boundary face (its Dirichlet
-    value is taken there); other ghost cells at their (unused) cell centres."""
+    """(120, B+2, B+2, B+2, 3) centres (x, y, z) of every stored cell, ghost cells included (a
+    ghost cell on the domain boundary takes its Dirichlet value at its centre, half a cell
+    outside the domain)."""
     blocks = block_list()
     m = B + 2
     out = np.empty((len(blocks), m, m, m, 3))
     i = np.arange(m) - 0.5
     for b, (lv, idx, w) in enumerate(blocks):
-        per = 4 if lv == 2 else 8
         h = w / B
         for a in range(3):
             c = idx[a] * w + i * h
-            if idx[a] == 0:
-                c[0] = 0.0
-            if idx[a] == per - 1:
-                c[-1] = 1.0
             shape = [1, 1, 1]
             shape[2 - a] = m  # array axes are [z][y][x]
             out[b, ..., a] = np.broadcast_to(c.reshape(shape), (m, m, m))
@@ -166,7 +161,7 @@ def block_harmonic(B: int):
 def block_harmonic_device(B: int, device):
     """block_harmonic's u0 built block by block with torch on `device` (the position array of
     block_harmonic would not fit the host at the largest block sizes): the Dirichlet data of
-    Eq. 2 at the face centres of the domain-boundary ghosts, 0 elsewhere."""
+    Eq. 2 at the centres of the domain-boundary ghosts, 0 elsewhere."""
     import torch
 
     m = B + 2
@@ -175,14 +170,7 @@ def block_harmonic_device(B: int, device):
     for b, (lv, idx, w) in enumerate(block_list()):
         per = 4 if lv == 2 else 8
         h = w / B
-        c = []
-        for a in range(3):
-            ca = idx[a] * w + i * h
-            if idx[a] == 0:
-                ca[0] = 0.0
-            if idx[a] == per - 1:
-                ca[-1] = 1.0
-            c.append(ca)
+        c = [idx[a] * w + i * h for a in range(3)]
         val = (torch.sin(np.pi * c[0])[None, None, :] * torch.sin(np.pi * c[1])[None, :, None]
                * torch.sinh(np.sqrt(2.0) * np.pi * c[2])[:, None, None])
         for a in range(3):

@@ -92,9 +92,7 @@ def gpu_solve(B, order):
     ug, info = rb.solve(f, ug, tol=1e-11 * r0, check_every=2000)
     u = host(ug)
     rb.close()
-    hb = np.array([w / B for (_, _, w) in inputs.block_list()])
-    e = (u - exact)[:, 1:-1, 1:-1, 1:-1].reshape(120, -1)
-    err = np.sqrt(np.sum(hb ** 3 * np.sum(e ** 2, axis=1)))
+    err = bl.rms_error(u[:, 1:-1, 1:-1, 1:-1], B)
     return u, err, info
 
 
@@ -111,9 +109,10 @@ def test_composite_solve_matches_oracle(order):
 
 
 def test_kappa_pattern_on_gpu():
-    """Table 1's pattern from GPU solves: quadratic C2F converges at second order (kappa 0.256
-    for 4 -> 8 cells per block and 0.252 for 8 -> 16, as the oracle gives), constant C2F does
-    not converge."""
+    """Table 1's pattern from GPU solves, against the oracle's values from its assembled
+    systems: quadratic C2F approaches second order from below (kappa 0.2101 for 4 -> 8 cells
+    per block, 0.2289 for 8 -> 16), constant C2F stays far from convergence (0.8498 for
+    4 -> 8)."""
     e = {}
     for order in (0, 2):
         for B in (4, 8, 16):
@@ -125,8 +124,8 @@ def test_kappa_pattern_on_gpu():
     k0 = e[(0, 8)] / e[(0, 4)]
     k2a, k2b = e[(2, 8)] / e[(2, 4)], e[(2, 16)] / e[(2, 8)]
     say(f"  kappa constant {k0:.4f}; quadratic {k2a:.4f}, {k2b:.4f}")
-    assert abs(k0 - 1.0) <= 0.05
-    assert abs(k2a - 0.2563) <= 2e-3 and abs(k2b - 0.2519) <= 2e-3
+    assert abs(k0 - 0.8498) <= 2e-3
+    assert abs(k2a - 0.2101) <= 2e-3 and abs(k2b - 0.2289) <= 2e-3
 
 
 # ---------------------------------------------------------------- multigrid (Sect. 5's solver)
@@ -217,7 +216,7 @@ def test_coarse_level_smoothing_matches_oracle():
     rb.smooth(1, torch.from_numpy(f).to(DEV), ug, 3)
     uo = u.copy().reshape(-1)
     for _ in range(3):
-        uo = bl.jacobi_sweep(uo, f.reshape(-1), Bc, order)
+        uo = bl.jacobi_sweep(uo, f.reshape(-1), Bc, order, coarse=True)
     got = host(ug)[:, 1:-1, 1:-1, 1:-1]
     want = uo.reshape(u.shape)[:, 1:-1, 1:-1, 1:-1]
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
@@ -287,7 +286,7 @@ def test_mg_solve_matches_composite_solution():
 
 def mg_error(B, order):
     """Sect. 5's run: V(3,3)-cycles until the L2 residual norm is below 1e-16 or 35 cycles,
-    then the volume-weighted L2 error against Eq. 2's exact solution."""
+    then Table 1's L2 error (root mean square over the cells) against Eq. 2's solution."""
     u0, exact = inputs.block_harmonic(B)
     rb = RefinedBlocks(B, order, device=DEV)
     f = torch.zeros(u0.shape, dtype=torch.float64, device=DEV)
@@ -295,9 +294,7 @@ def mg_error(B, order):
     ug, info = rb.mg_solve(f, ug, tol=1e-16)
     u = host(ug)
     rb.close()
-    hb = np.array([w / B for (_, _, w) in inputs.block_list()])
-    e = (u - exact)[:, 1:-1, 1:-1, 1:-1].reshape(120, -1)
-    return float(np.sqrt(np.sum(hb ** 3 * np.sum(e ** 2, axis=1)))), info
+    return bl.rms_error(u[:, 1:-1, 1:-1, 1:-1], B), info
 
 
 def mg_error_device(B, order):
@@ -317,26 +314,46 @@ def mg_error_device(B, order):
         ex = (torch.sin(math.pi * x)[None, None, :] * torch.sin(math.pi * y)[None, :, None]
               * torch.sinh(math.sqrt(2.0) * math.pi * z)[:, None, None])
         d = u[b, 1:-1, 1:-1, 1:-1] - ex
-        total += h ** 3 * float(torch.sum(d * d))
-    return math.sqrt(total), info
+        total += float(torch.sum(d * d))
+    return math.sqrt(total / (120 * B ** 3)), info
 
 
-def test_table1_pattern_with_multigrid():
-    """Table 1's experiment with the paper's solver at block sizes 16, 32, 64 and 128:
-    constant C2F does not converge (kappa ~ 1), linear C2F is first order (kappa rising
-    towards 0.5), quadratic C2F second order (kappa within Table 1's deviation from 0.25)."""
+def _printed_table1():
+    """Table 1 (Sect. 5) as printed: {order: {block size: (value, half a unit of the last
+    printed digit)}}."""
+    import decimal
+    import os
+
+    out = {0: {}, 1: {}, 2: {}}
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_table1_errors.txt")
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        b, *cols = line.split()
+        for order, txt in zip((0, 1, 2), cols):
+            d = decimal.Decimal(txt)
+            out[order][int(b)] = (float(d), 0.5 * 10.0 ** d.as_tuple().exponent)
+    return out
+
+
+def test_table1_with_multigrid():
+    """Table 1's experiment with the paper's solver (35 V(3,3)-cycles, Sect. 5) at block sizes
+    16, 32, 64 and 128: the errors of all three C2F orders agree with the printed values to
+    their last printed digit (Dirichlet data at the boundary ghost centres, the error as the
+    root mean square over all cells), and the first-order column's kappa is near 0.5."""
+    printed = _printed_table1()
     e = {}
     for order in (0, 1, 2):
         for B in (16, 32, 64, 128):
             e[(order, B)], info = mg_error(B, order) if B <= 64 else mg_error_device(B, order)
-            say(f"  order {order} B={B}: L2 error {e[(order, B)]:.4e} ({info.cycles} cycles, "
-                f"residual {info.relres:.2e})")
+            val, half = printed[order][B]
+            say(f"  order {order} B={B}: L2 error {e[(order, B)]:.5e} (paper {val:g}; "
+                f"{info.cycles} cycles, residual {info.relres:.2e})")
             assert info.cycles == 35
-    k = {o: (e[(o, 32)] / e[(o, 16)], e[(o, 64)] / e[(o, 32)], e[(o, 128)] / e[(o, 64)]) for o in (0, 1, 2)}
-    say(f"  kappa {k}")
-    assert all(abs(x - 1.0) <= 0.05 for x in k[0])
-    assert 0.4 <= k[1][0] <= k[1][1] <= k[1][2] <= 0.55
-    assert all(abs(x - 0.25) <= 0.011 for x in k[2])
+            assert abs(e[(order, B)] - val) <= 1.1 * half, (order, B, e[(order, B)], val)
+    k1 = [e[(1, b)] / e[(1, a)] for a, b in ((16, 32), (32, 64), (64, 128))]
+    say(f"  first-order kappa {k1}")
+    assert all(0.45 <= k <= 0.55 for k in k1)
     # the device generator and error agree with the host ones where both fit
     e64, _ = mg_error_device(64, 2)
     assert abs(e64 - e[(2, 64)]) <= 1e-9 * e[(2, 64)]
