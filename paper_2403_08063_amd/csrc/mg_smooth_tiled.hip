@@ -583,8 +583,9 @@ LaunchShape shape_for(int n, int capacity)
   return L;
 }
 
-// Tile shape (waves x rows per wave) and prefetch depth per pass, from timing sweeps on
-// MI355X at 513^3: the second prefetch buffer is used wherever it keeps the occupancy.
+// Tile shape (waves x rows per wave), prefetch depth and whether the 64-column layout is
+// compiled, per pass, from timing sweeps on MI355X at 513^3 (the FP32 passes of the
+// refinement cycle were timed inside the whole solve).
 #ifndef MG_SMOOTH_W
 #define MG_SMOOTH_W 8
 #endif
@@ -592,10 +593,10 @@ LaunchShape shape_for(int n, int capacity)
 #define MG_SMOOTH_RPW 4
 #endif
 #ifndef MG_SMOOTH32_PROLONG_W
-#define MG_SMOOTH32_PROLONG_W 12
+#define MG_SMOOTH32_PROLONG_W 8
 #endif
 #ifndef MG_SMOOTH32_PROLONG_PD
-#define MG_SMOOTH32_PROLONG_PD 2
+#define MG_SMOOTH32_PROLONG_PD 1
 #endif
 #ifndef MG_SMOOTH32_ZERO_PD
 #define MG_SMOOTH32_ZERO_PD 2
@@ -616,22 +617,22 @@ LaunchShape shape_for(int n, int capacity)
 #define MG_SMOOTH32_RES_W 8
 #endif
 #ifndef MG_SMOOTH32_RES_RPW
-#define MG_SMOOTH32_RES_RPW 6
+#define MG_SMOOTH32_RES_RPW 4
 #endif
 #ifndef MG_SMOOTH32_PROLONG_RPW
-#define MG_SMOOTH32_PROLONG_RPW 4
+#define MG_SMOOTH32_PROLONG_RPW 6
 #endif
 #ifndef MG_SMOOTH32_READ_RPW
 #define MG_SMOOTH32_READ_RPW 4
 #endif
 #ifndef MG_SMOOTH32_RES_PD
-#define MG_SMOOTH32_RES_PD 2
+#define MG_SMOOTH32_RES_PD 1
 #endif
 #ifndef MG_SMOOTH32_RES_NARROW
-#define MG_SMOOTH32_RES_NARROW 0
+#define MG_SMOOTH32_RES_NARROW 1
 #endif
 #ifndef MG_SMOOTH32_PROLONG_NARROW
-#define MG_SMOOTH32_PROLONG_NARROW 0
+#define MG_SMOOTH32_PROLONG_NARROW 1
 #endif
 template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
@@ -652,8 +653,9 @@ struct Shape {
                             : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
                                                : (f32 ? MG_SMOOTH32_READ_PD : 1);
   // whether the 64-column layout (LW = 32) is compiled for this pass: its per-lane row
-  // offsets cost ~20-30 VGPRs, which the FP64 variable-coefficient pass does not have to
-  // spare (it would spill)
+  // offsets cost ~20-40 VGPRs, which the FP64 variable-coefficient pass does not have to
+  // spare (it would spill; so would the FP32 restriction and prolongation passes with a
+  // second prefetch buffer or 6 rows per wave in the restriction)
   static constexpr bool NARROW = RES ? MG_SMOOTH32_RES_NARROW
                                  : IN == kInProlong ? MG_SMOOTH32_PROLONG_NARROW
                                                     : !(VAR && !f32);
