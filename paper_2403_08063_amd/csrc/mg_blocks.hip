@@ -389,6 +389,23 @@ __device__ __forceinline__ double blk_apply_at(int B, const int* __restrict__ fb
   return s * ih2;
 }
 
+// (A u) at a cell from its value c and its six neighbours' values v (-x, +x, -y, +y, -z, +z),
+// as blk_apply_at forms it; bnd bit a: neighbour a is a domain-boundary ghost
+__device__ __forceinline__ double blk_apply_vals(double ih2, double c, const double (&v)[6],
+                                                 unsigned bnd, bool coarse)
+{
+  double w[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) w[a] = (coarse && ((bnd >> a) & 1u)) ? 2.0 * v[a] - c : v[a];
+  double s = c - w[0];
+  s = s + (c - w[1]);
+  s = s + (c - w[2]);
+  s = s + (c - w[3]);
+  s = s + (c - w[4]);
+  s = s + (c - w[5]);
+  return s * ih2;
+}
+
 // One thread per inner cell of all blocks of size B, 256 threads per workgroup: for B >= 64
 // a workgroup covers 64 x 4 cells of an (x, y) plane (grid: x tiles, y tiles, blocks x B
 // planes); for smaller blocks a flat index over the blocks' cells (B^3 >= 64 cells a block).
@@ -450,6 +467,47 @@ __global__ void __launch_bounds__(kCellThreads)
   int b, z, y, x;
   if (!cell_of(B, b, z, y, x)) return;
   jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, z, y, x);
+}
+
+// Damped-Jacobi sweep of blocks of >= 64 cells a side, marching along z: a thread owns
+// column (x, y) of a 64 x 4-cell tile of one block for kZRun consecutive planes and keeps
+// u of the planes z-1, z, z+1 in registers, so each u value is loaded once by its column
+// instead of once per z-neighbour; x and y neighbours come from the caches.  Per cell the
+// operations of jacobi_cell.  Grid: (B/64, B/4, blocks x B/kZRun).
+constexpr int kZRun = 8;
+__global__ void __launch_bounds__(kCellThreads)
+    k_blk_jacobi_z(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
+                   const double* __restrict__ f, const double* __restrict__ u,
+                   double* __restrict__ uout, int coarse)
+{
+  const int x = 1 + blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = 1 + blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x > B || y > B) return;
+  const int runs = B / kZRun;
+  const int b = blockIdx.z / runs;
+  const int z0 = 1 + (blockIdx.z % runs) * kZRun;
+  const int m = B + 2;
+  const size_t sy = (size_t)m, sz = (size_t)m * m;
+  const double h = hs[b];
+  const double ih2 = 1.0 / (h * h), coef = omega * (h * h / 6.0);
+  const int* fb = faces + (size_t)b * 6 * kFaceInts;
+  const unsigned bxy = (x == 1 && fb[0 * kFaceInts] == kFaceBoundary ? 1u : 0u) |
+                       (x == B && fb[1 * kFaceInts] == kFaceBoundary ? 2u : 0u) |
+                       (y == 1 && fb[2 * kFaceInts] == kFaceBoundary ? 4u : 0u) |
+                       (y == B && fb[3 * kFaceInts] == kFaceBoundary ? 8u : 0u);
+  const bool zlo = fb[4 * kFaceInts] == kFaceBoundary, zhi = fb[5 * kFaceInts] == kFaceBoundary;
+  size_t i = bidx(m, b, z0, y, x);
+  double zm = u[i - sz], c = u[i];
+  for (int k = 0; k < kZRun; ++k, i += sz) {
+    const int z = z0 + k;
+    const double zp = u[i + sz];
+    const double v[6] = {u[i - 1], u[i + 1], u[i - sy], u[i + sy], zm, zp};
+    const unsigned bnd = bxy | (z == 1 && zlo ? 16u : 0u) | (z == B && zhi ? 32u : 0u);
+    const double au = blk_apply_vals(ih2, c, v, bnd, coarse != 0);
+    uout[i] = c + coef * (f[i] - au);
+    zm = c;
+    c = zp;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -589,9 +647,14 @@ double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, i
   const BlkLevel& L = c->lv[l];
   const int B = L.B;
   const dim3 grid = cell_grid(B);
+  const bool zrun = B >= kCellRowsMin && B % kZRun == 0;
+  const dim3 zgrid((unsigned)((B + 63) / 64), (unsigned)((B + 3) / 4), (unsigned)(kBlocks * (B / kZRun)));
   for (int s = 0; s < count; ++s) {
     fill(c, l, cur);
-    k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
+    if (zrun)
+      k_blk_jacobi_z<<<zgrid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
+    else
+      k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
     double* x = cur;
     cur = oth;
     oth = x;
