@@ -474,7 +474,10 @@ __global__ void __launch_bounds__(kCellThreads)
 // u of the planes z-1, z, z+1 in registers, so each u value is loaded once by its column
 // instead of once per z-neighbour; x and y neighbours come from the caches.  Per cell the
 // operations of jacobi_cell.  Grid: (B/64, B/4, blocks x B/kZRun).
-constexpr int kZRun = 8;
+#ifndef MG_BLK_ZRUN
+#define MG_BLK_ZRUN 8
+#endif
+constexpr int kZRun = MG_BLK_ZRUN;
 __global__ void __launch_bounds__(kCellThreads)
     k_blk_jacobi_z(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
                    const double* __restrict__ f, const double* __restrict__ u,
@@ -610,6 +613,124 @@ __global__ void __launch_bounds__(kCellThreads)
   u[i] = u[i] + 0.25 * (((eP + ex) + ey) + ez);
 }
 
+// Residual restriction for fine blocks of >= 128 cells a side (coarse >= 64), marching along
+// z: a thread owns coarse column (X, Y) of a 64 x 4 coarse tile for kZRun coarse planes and
+// keeps the 2 x 2 fine columns of the planes 2Z .. 2Z+3 it needs in registers (the upper two
+// are the next coarse plane's lower two).  Per child the operations of k_blk_restrict, summed
+// in the same order.  Grid: (Bc/64, Bc/4, blocks x Bc/kZRun).
+__global__ void __launch_bounds__(kCellThreads)
+    k_blk_restrict_z(int B, const int* __restrict__ faces, const double* __restrict__ hs,
+                     const double* __restrict__ f, const double* __restrict__ u,
+                     double* __restrict__ fc, double* __restrict__ uc, int coarse)
+{
+  const int Bc = B / 2;
+  const int X = blockIdx.x * 64 + (threadIdx.x & 63), Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (X >= Bc || Y >= Bc) return;  // 0-based coarse indices
+  const int runs = Bc / kZRun;
+  const int b = blockIdx.z / runs;
+  const int Z0 = (blockIdx.z % runs) * kZRun;
+  const int m = B + 2, mc = Bc + 2;
+  const size_t sy = (size_t)m;
+  const double h = hs[b];
+  const double ih2 = 1.0 / (h * h);
+  const int* fb = faces + (size_t)b * 6 * kFaceInts;
+  const int x0 = 1 + 2 * X, y0 = 1 + 2 * Y;  // first child column and row
+  unsigned bxy[2][2];  // per child (dy, dx): x/y neighbours on the domain boundary
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      const int x = x0 + dx, y = y0 + dy;
+      bxy[dy][dx] = (x == 1 && fb[0 * kFaceInts] == kFaceBoundary ? 1u : 0u) |
+                    (x == B && fb[1 * kFaceInts] == kFaceBoundary ? 2u : 0u) |
+                    (y == 1 && fb[2 * kFaceInts] == kFaceBoundary ? 4u : 0u) |
+                    (y == B && fb[3 * kFaceInts] == kFaceBoundary ? 8u : 0u);
+    }
+  const bool zlo = fb[4 * kFaceInts] == kFaceBoundary, zhi = fb[5 * kFaceInts] == kFaceBoundary;
+  // P[q][dy][dx]: u of fine plane 2Z + q (q = 0..3) at the child column (dy, dx)
+  double P[4][2][2];
+  auto load_plane = [&](int q, int z) {
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) P[q][dy][dx] = u[bidx(m, b, z, y0 + dy, x0 + dx)];
+  };
+  load_plane(0, 2 * Z0);
+  load_plane(1, 2 * Z0 + 1);
+  for (int k = 0; k < kZRun; ++k) {
+    const int Z = Z0 + k;
+    load_plane(2, 2 * Z + 2);
+    load_plane(3, 2 * Z + 3);
+    double s = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int z = 1 + 2 * Z + dz, y = y0 + dy, x = x0 + dx;
+          const size_t i = bidx(m, b, z, y, x);
+          const double c = P[1 + dz][dy][dx];
+          const double v[6] = {dx ? P[1 + dz][dy][0] : u[i - 1], dx ? u[i + 1] : P[1 + dz][dy][1],
+                               dy ? P[1 + dz][0][dx] : u[i - sy], dy ? u[i + sy] : P[1 + dz][1][dx],
+                               P[dz][dy][dx], P[2 + dz][dy][dx]};
+          const unsigned bnd = bxy[dy][dx] | (z == 1 && zlo ? 16u : 0u) | (z == B && zhi ? 32u : 0u);
+          const double r = f[i] - blk_apply_vals(ih2, c, v, bnd, coarse != 0);
+          s = first ? r : s + r;
+          first = false;
+        }
+    const size_t ci = bidx(mc, b, Z + 1, Y + 1, X + 1);
+    fc[ci] = 0.125 * s;
+    if (uc) uc[ci] = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        P[0][dy][dx] = P[2][dy][dx];
+        P[1][dy][dx] = P[3][dy][dx];
+      }
+  }
+}
+
+// u += P e for fine blocks of >= 64 cells a side, marching along z: a thread owns fine column
+// (x, y) of a 64 x 4 tile for kZRun fine planes; the parent and its x and y neighbours are
+// the same for the two fine planes of a coarse plane.  Per cell the operations of
+// k_blk_prolong.  Grid: (B/64, B/4, blocks x B/kZRun).
+__global__ void __launch_bounds__(kCellThreads)
+    k_blk_prolong_z(int B, const int* __restrict__ faces, const double* __restrict__ e,
+                    double* __restrict__ u)
+{
+  const int x1 = 1 + blockIdx.x * 64 + (threadIdx.x & 63), y1 = 1 + blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x1 > B || y1 > B) return;
+  const int runs = B / kZRun;
+  const int b = blockIdx.z / runs;
+  const int zs = (blockIdx.z % runs) * kZRun;  // first 0-based fine plane (even)
+  const int x0 = x1 - 1, y0 = y1 - 1;
+  const int Bc = B / 2, mc = Bc + 2;
+  const int* fb = faces + (size_t)b * 6 * kFaceInts;
+  const int X = 1 + x0 / 2, Y = 1 + y0 / 2;
+  const int dx = (x0 & 1) ? 1 : -1, dy = (y0 & 1) ? 1 : -1;
+  auto across = [&](int n, int face) {
+    return (n == 0 || n == Bc + 1) && fb[face * kFaceInts] == kFaceBoundary;
+  };
+  const bool ax = across(X + dx, (x0 & 1)), ay = across(Y + dy, 2 + (y0 & 1));
+  size_t i = bidx(B + 2, b, zs + 1, y1, x1);
+  const size_t sz = (size_t)(B + 2) * (B + 2);
+  for (int k = 0; k < kZRun; k += 2) {
+    const int Z = 1 + (zs + k) / 2;
+    const double eP = e[bidx(mc, b, Z, Y, X)];
+    const double ex = ax ? -eP : e[bidx(mc, b, Z, Y, X + dx)];
+    const double ey = ay ? -eP : e[bidx(mc, b, Z, Y + dy, X)];
+#pragma unroll
+    for (int j = 0; j < 2; ++j, i += sz) {
+      const int dz = j ? 1 : -1;  // 0-based fine plane zs + k + j: even -> -1, odd -> +1
+      const double ez = across(Z + dz, 4 + j) ? -eP : e[bidx(mc, b, Z + dz, Y, X)];
+      u[i] = u[i] + 0.25 * (((eP + ex) + ey) + ez);
+    }
+  }
+}
+
 // dst = src on the domain-boundary ghost cells (the Dirichlet data of the second buffer)
 __global__ void __launch_bounds__(kFillThreads)
     k_blk_copy_boundary(int B, const int* __restrict__ faces, const double* __restrict__ src,
@@ -668,7 +789,12 @@ void restrict_residual(mgblk_ctx* c, int l, const double* f, double* u, double* 
   const BlkLevel& L = c->lv[l];
   const int Bc = L.B / 2;
   fill(c, l, u);
-  k_blk_restrict<<<cell_grid(Bc), kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc, l > 0);
+  if (Bc >= kCellRowsMin && Bc % kZRun == 0)
+    k_blk_restrict_z<<<dim3((unsigned)((Bc + 63) / 64), (unsigned)((Bc + 3) / 4),
+                            (unsigned)(kBlocks * (Bc / kZRun))),
+                       kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc, l > 0);
+  else
+    k_blk_restrict<<<cell_grid(Bc), kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc, l > 0);
 }
 
 // fills ec's interface ghosts (level l+1), then u (level l) += P ec
@@ -676,7 +802,12 @@ void prolong_correct(mgblk_ctx* c, int l, double* ec, double* u)
 {
   const int B = c->lv[l].B;
   fill(c, l + 1, ec);
-  k_blk_prolong<<<cell_grid(B), kCellThreads, 0, c->s>>>(B, c->faces, ec, u);
+  if (B >= kCellRowsMin && B % kZRun == 0)
+    k_blk_prolong_z<<<dim3((unsigned)((B + 63) / 64), (unsigned)((B + 3) / 4),
+                           (unsigned)(kBlocks * (B / kZRun))),
+                      kCellThreads, 0, c->s>>>(B, c->faces, ec, u);
+  else
+    k_blk_prolong<<<cell_grid(B), kCellThreads, 0, c->s>>>(B, c->faces, ec, u);
 }
 
 // V(nu1, nu2) on level l from the iterate in x (y: the level's second buffer); returns the
