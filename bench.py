@@ -132,14 +132,16 @@ def pmc_ir_sample(n: int):
 
 
 # Algorithmic bytes per interior node of the fine-level kernels of the FP32-refined solve,
-# by kernel-name pattern: (pattern, what it is, bytes per node)
+# by kernel-name pattern (a regular expression on the short name: value type, variable
+# coefficient, sweeps, then any tile shape, then input mode and fused restriction):
+# (pattern, what it is, bytes per node)
 IR_KERNELS = [
-    ("k_rbgs_tiled<float, false, 2, 8, 6, 2, 1, 1", "FP32 pre-smoothing from 0 + residual restriction",
+    (r"k_rbgs_tiled<float, false, 2, \d+, \d+, \d+, 1, 1", "FP32 pre-smoothing from 0 + residual restriction",
      4 + 4 + 0.5),
-    ("k_rbgs_tiled<float, false, 2, 12, 4, 2, 2, 0", "FP32 post-smoothing with the prolongation",
+    (r"k_rbgs_tiled<float, false, 2, \d+, \d+, \d+, 2, 0", "FP32 post-smoothing with the prolongation",
      4 + 4 + 4 + 0.5),
-    ("k_pass<false, 2,", "refinement pass (u += s e, r = f - A u, norm, r32)", 8 + 8 + 4 + 8 + 4),
-    ("k_pass<false, 6,", "first refinement pass (+ right-hand-side norm)", 8 + 8 + 8 + 4),
+    (r"k_pass<false, 2,", "refinement pass (u += s e, r = f - A u, norm, r32)", 8 + 8 + 4 + 8 + 4),
+    (r"k_pass<false, 6,", "first refinement pass (+ right-hand-side norm)", 8 + 8 + 8 + 4),
 ]
 
 
@@ -150,6 +152,7 @@ def summarize_pmc_kernels(fetch_dir: str, write_dir: str, n: int):
     table on stdout."""
     import csv
     import glob
+    import re
 
     meas = {}
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
@@ -163,21 +166,21 @@ def summarize_pmc_kernels(fetch_dir: str, write_dir: str, n: int):
             raise SystemExit(f"{counter}: no calibration copy in {d}")
         factor = (CALIB_BYTES / 1024.0) / copy[0]
         for pat, _, _ in IR_KERNELS:
-            vals = [v for name, v in rows if name.startswith(pat)]
+            vals = [v for name, v in rows if re.match(pat, name)]
             if not vals:
                 continue
             top = max(vals)
             fine = [v for v in vals if v >= 0.5 * top]  # the fine-level dispatches
             meas.setdefault(pat, {})[key] = (sum(fine) / len(fine) * 1024.0 * factor, len(fine), factor)
     m = (n - 2) ** 3
-    print(f"| kernel | what | fine-level dispatches | FETCH bytes | WRITE bytes | measured / algorithmic |")
+    print("| kernel (name pattern) | what | fine-level dispatches | FETCH bytes | WRITE bytes | measured / algorithmic |")
     print("|---|---|---:|---:|---:|---:|")
     for pat, what, bpn in IR_KERNELS:
         if pat not in meas or len(meas[pat]) < 2:
             continue
         fb, cnt, _ = meas[pat]["fetch"]
         wb, _, _ = meas[pat]["write"]
-        print(f"| `{pat}...>` | {what} | {cnt} | {fb:.3e} | {wb:.3e} | "
+        print(f"| `{pat}` | {what} | {cnt} | {fb:.3e} | {wb:.3e} | "
               f"{(fb + wb) / (bpn * m):.3f} ({bpn:g} B per node) |")
 
 
