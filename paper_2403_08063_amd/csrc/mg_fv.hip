@@ -396,8 +396,15 @@ double* cycle(mgfv_ctx* c, int l, double* u, double* t, const double* f)
   restrict_residual(c, l, f, cur, C.f);
   mgk::fill<double>(c->s, C.cnt, 0.0, C.u);  // zero correction, zero Dirichlet data
   double* ec = cycle(c, l + 1, C.u, C.t, C.f);
+  double* oth = cur == u ? t : u;
+  const FvLevel& F = c->lv[l];
+  if (c->g.nu2 > 0 && mgk::fv_tiled_supported(F.N)) {
+    // the correction enters the first post-smoothing sweep: u + P e is never stored
+    mgk::fv_jacobi_prolong_tiled(c->s, F.N, F.h, c->g.omega, f, cur, ec, oth, c->partial);
+    return smooth(c, l, oth, cur, f, c->g.nu2 - 1);
+  }
   prolong(c, l, ec, cur);
-  return smooth(c, l, cur, cur == u ? t : u, f, c->g.nu2);
+  return smooth(c, l, cur, oth, f, c->g.nu2);
 }
 
 mg_status read_norm(mgfv_ctx* c, double* out)

@@ -137,6 +137,11 @@ bool fv_tiled_supported(int N);
 // one damped Jacobi sweep, uout = u + omega h^2/6 (f - A u) on the cells (ghosts untouched)
 void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double* f,
                      const double* u, double* uout, double* partial);
+// the first post-smoothing sweep of a V-cycle: uout = Jacobi(u + P ec), with ec the coarse
+// correction ((N/2 + 2)^3 values, ghost layer not read) interpolated as the stand-alone
+// prolongation does; u itself is not modified
+void fv_jacobi_prolong_tiled(hipStream_t s, int N, double h, double omega, const double* f,
+                             const double* u, const double* ec, double* uout, double* partial);
 // fc = mean of the 8 children's residuals f - A u on the coarse cells (N/2 per side);
 // fc's ghost layer is not written
 void fv_restrict_tiled(hipStream_t s, int N, double h, const double* f, const double* u,

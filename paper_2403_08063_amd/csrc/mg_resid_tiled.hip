@@ -37,7 +37,21 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4, kFvRestrict = 5,
-       kRefineRhs = 6 };
+       kRefineRhs = 6, kFvJacobiProlong = 7 };
+
+// Shape of the finite-volume sweep with the prolongation from N = 256 on (waves, rows per
+// wave, column pairs per lane), from timing sweeps on MI355X at 512^3 cells: 128 x 32-cell
+// tiles (two row pairs per lane; the interpolation needs the registers a second column pair
+// would take).
+#ifndef MG_FV_PROLONG_CP
+#define MG_FV_PROLONG_CP 1
+#endif
+#ifndef MG_FV_PROLONG_W
+#define MG_FV_PROLONG_W 8
+#endif
+#ifndef MG_FV_PROLONG_RPW
+#define MG_FV_PROLONG_RPW 4
+#endif
 
 // (A u)_i of the cell-centred finite-volume operator from the six neighbour values (ghost
 // neighbours already replaced by 2 g - u_i), in the order -x, +x, -y, +y, -z, +z.
@@ -331,23 +345,38 @@ struct Stream {
 // kFvRestrict writes the mean of the 8 children's residuals to the coarse level: a lane's
 // column pair, a wave's row pair and a pair of consecutive planes (z-chunks of even length
 // starting on odd planes) are the children of one coarse cell, summed in the order z, y, x.
+// kFvJacobiProlong is the Jacobi sweep of u + P e: the coarse-grid correction e (N/2 cells
+// per side) is interpolated onto every fine value the sweep reads -- the lane's own cells,
+// the halo column and the halo row -- once they are in registers, so the corrected iterate
+// is never stored.  The tile's coarse region (the parents of its cells, the halo's parents
+// and one coarse cell around them) is staged plane by plane in LDS: a ring of three coarse
+// planes, one new plane every second fine plane.  Each fine value sums its 8 weighted
+// coarse terms in the order z, y, x, parent first (the stand-alone prolongation's order).
 template <bool VAR, int MODE, int W, int RPW, int CP>
 struct Pass {
-  static constexpr bool FV = MODE == kFvNorm || MODE == kFvJacobi || MODE == kFvRestrict;
+  static constexpr bool PRO = MODE == kFvJacobiProlong;
+  static constexpr bool JAC = MODE == kFvJacobi || PRO;  // writes a Jacobi update
+  static constexpr bool FV = MODE == kFvNorm || JAC || MODE == kFvRestrict;
   // refinement pass; kRefineRhs (the first pass of a solve, no correction) also sums the
   // squares of the full right-hand side b = f - A u_B (u_B: the Dirichlet data of u with a
   // zero interior), with the operations of the norm pass reading the interior of u as 0
   static constexpr bool REFINE = MODE == kRefine || MODE == kRefineRhs;
   static constexpr bool RHS = MODE == kRefineRhs;
   static_assert(MODE != kFvRestrict || RPW % 2 == 0, "row pairs of the restriction");
+  static_assert(!PRO || RPW % 2 == 0, "row pairs share their coarse parents");
   static_assert(!(FV && VAR), "the finite-volume scheme has a constant coefficient");
   static_assert(W >= 2, "the first and the last wave load the tile's halo rows");
   static constexpr int BX = 128 * CP, BY = W * RPW;
   static constexpr int NE = RPW > 1 ? 2 : 1;  // edge rows of a wave: first, last
+  // prolongation: coarse rows and columns staged per coarse plane (parents of the tile's
+  // BY rows and BX columns and one more on each side), values loaded per thread
+  static constexpr int CRY = PRO ? BY / 2 + 2 : 1, CRX = PRO ? 64 * CP + 2 : 1;
+  static constexpr int CLD = PRO ? (CRY * CRX + 64 * W - 1) / (64 * W) : 1;
 
   struct Shared {
     double eu[2][W][NE][CP][2][64];  // [buffer][wave][first/last row][pair][column][lane]
     double ek[VAR ? 2 : 1][VAR ? W : 1][VAR ? NE : 1][VAR ? CP : 1][2][64];
+    double cz[PRO ? 3 : 1][CRY * CRX];  // prolongation: coarse plane Z in slot Z mod 3
     double red[W];
     double redb[W];
   };
@@ -363,6 +392,7 @@ struct Pass {
     double scale;        // refinement: u_out = u + scale * e
     double inv_scale;    // refinement: r32 = r * inv_scale
     double coef;         // finite-volume Jacobi: u_out = u + coef * (f - A u)
+    const double* ec;    // finite-volume prolongation: coarse correction, (N/2 + 2)^3
     int zero_interior;   // norm: read the interior of u as 0
     int n;
     double ih2;
@@ -437,6 +467,75 @@ struct Pass {
       gyp[i] = gy + 1 == n - 1;
     }
 
+    // Prolongation (u + P e): the coarse region's origin is the parent of the tile's first
+    // cell minus one; a lane's rows 2i', 2i'+1 (global rows odd, even) share the parent row
+    // wave*RPW/2 + i' + 1 of the region and take the row below / above as the neighbour; its
+    // column pair shares the parent column 64 p + lane + 1 (neighbour left / right).  The
+    // halo column is the parent's right half (lane 0: parent 0, neighbour 1) or left half
+    // (lane 63: parent 64 CP + 1, neighbour 64 CP); likewise the halo rows.
+    const int cxo = (ox + 1) / 2 - 1, cyo = (oy + 1) / 2 - 1;
+    const int ncs = (n - 2) / 2;  // coarse cells per side
+    auto cload = [&](int Zc, double (&R)[CLD]) {
+#pragma unroll
+      for (int k = 0; k < CLD; ++k) {
+        const int t = (int)threadIdx.x + k * 64 * W;
+        double v = 0.0;
+        if (t < CRY * CRX) {
+          const int ly = t / CRX, lx = t - ly * CRX;
+          int Z = Zc, Y = cyo + ly, X = cxo + lx;
+          if (Z >= 0 && Z <= ncs + 1 && Y <= ncs + 1 && X <= ncs + 1) {
+            // the ghost layer holds the homogeneous extension: minus the adjacent cell
+            double sg = 1.0;
+            if (Z == 0) { Z = 1; sg = -sg; }
+            if (Z == ncs + 1) { Z = ncs; sg = -sg; }
+            if (Y == 0) { Y = 1; sg = -sg; }
+            if (Y == ncs + 1) { Y = ncs; sg = -sg; }
+            if (X == 0) { X = 1; sg = -sg; }
+            if (X == ncs + 1) { X = ncs; sg = -sg; }
+            const size_t mc = (size_t)ncs + 2;
+            v = sg * a.ec[((size_t)Z * mc + (size_t)Y) * mc + (size_t)X];
+          }
+        }
+        R[k] = v;
+      }
+    };
+    auto cstore = [&](int Zc, const double (&R)[CLD]) {
+      double* d = sh.cz[PRO ? Zc % 3 : 0];
+#pragma unroll
+      for (int k = 0; k < CLD; ++k) {
+        const int t = (int)threadIdx.x + k * 64 * W;
+        if (t < CRY * CRX) d[t] = R[k];
+      }
+    };
+    // P e of a fine cell sums 8 terms in the order z, y, x, parent first: on the parent
+    // plane the parent row (parent column, then the neighbour column) and the neighbour row,
+    // then the same on the neighbour plane, with the weights kWp (parent column) and kWq
+    // (neighbour column) of those four rows: products of 3/4 and 1/4, exact.
+    constexpr double kWp[4] = {0.421875, 0.140625, 0.140625, 0.046875};
+    constexpr double kWq[4] = {0.140625, 0.046875, 0.046875, 0.015625};
+    auto planes_of = [&](int z, const double*& cp, const double*& cq) {
+      const int pz = (z + 1) >> 1, qz = (z & 1) ? pz - 1 : pz + 1;
+      cp = sh.cz[PRO ? pz % 3 : 0];
+      cq = sh.cz[PRO ? qz % 3 : 0];
+    };
+    // P e at region rows yp (parent), yq (neighbour) and columns xp, xq of the two planes
+    auto pe = [&](const double* cp, const double* cq, int yp, int yq, int xp, int xq) {
+      double e = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double* row = (k < 2 ? cp : cq) + (k % 2 ? yq : yp) * CRX;
+        const double e1 = e + kWp[k] * row[xp];
+        e = e1 + kWq[k] * row[xq];
+      }
+      return e;
+    };
+    const int lyw = w * (RPW / 2) + 1;  // parent row (region) of the wave's first row pair
+    const int hyp = w == 0 ? 0 : BY / 2 + 1, hyq = w == 0 ? 1 : BY / 2;
+    double CR[CLD];                        // the coarse plane to be staged next
+    double EXn[PRO ? RPW : 1], EXo[PRO ? RPW : 1];  // halo column's P e: last plane, the one before
+#pragma unroll
+    for (int i = 0; i < (PRO ? RPW : 1); ++i) EXn[i] = EXo[i] = 0.0;
+
     // Norm with zero_interior reads interior values of u as 0; the refinement pass adds
     // scale * e to them.
     auto adjust = [&](double v, float ev, bool in) -> double {
@@ -485,6 +584,58 @@ struct Pass {
 #pragma unroll
           for (int p = 0; p < CP; ++p) buf_load2(be, cf[p], rb4[i], PE[i][p][0], PE[i][p][1]);
       }
+    };
+    // u + P e on plane z, the last plane of the queue (U[2]), for the lane's cells; the
+    // halo column's values of plane z are kept until plane z is computed
+    auto prolong_in = [&](int z) {
+      const bool zin = z >= 1 && z <= n - 2;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) EXo[i] = EXn[i];
+      if (!zin) return;
+      const double *cp, *cq;
+      planes_of(z, cp, cq);
+#pragma unroll
+      for (int i2 = 0; i2 < RPW / 2; ++i2) {
+        const int yp = lyw + i2;
+        // rows 2 i2 (odd: neighbour row below) and 2 i2 + 1 (even: above)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int i = 2 * i2 + j;
+          if (!rin[i]) continue;
+          const int yq = j ? yp + 1 : yp - 1;
+#pragma unroll
+          for (int p = 0; p < CP; ++p)
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+              const int xp = 64 * p + lane + 1;
+              const double e = pe(cp, cq, yp, yq, xp, o ? xp + 1 : xp - 1);
+              if (o ? in1[p] : in0[p]) U[2][i][p][o] = U[2][i][p][o] + e;
+            }
+          EXn[i] = pe(cp, cq, yp, yq, lane == 63 ? 64 * CP + 1 : 0, lane == 63 ? 64 * CP : 1);
+        }
+      }
+    };
+    // u + P e on plane s's halo column (kept from prolong_in) and halo row
+    auto prolong_halo = [&](int s) {
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+        if (rin[i] && hcin) X[i] = X[i] + EXo[i];
+      if (!(hw && hyin)) return;
+      const double *cp, *cq;
+      planes_of(s, cp, cq);
+      double E[CP][2];
+#pragma unroll
+      for (int p = 0; p < CP; ++p)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          const int xp = 64 * p + lane + 1;
+          E[p][o] = pe(cp, cq, hyp, hyq, xp, o ? xp + 1 : xp - 1);
+        }
+#pragma unroll
+      for (int p = 0; p < CP; ++p)
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+          if (o ? in1[p] : in0[p]) H[p][o] = H[p][o] + E[p][o];
     };
     auto shift_in = [&](int z) {
       const bool zin = z >= 1 && z <= n - 2;
@@ -559,7 +710,7 @@ struct Pass {
     };
 
     float RK[RPW][CP][2];
-    double JV[MODE == kFvJacobi ? RPW : 1][CP][2];
+    double JV[JAC ? RPW : 1][CP][2];
     double RA[MODE == kFvRestrict ? RPW / 2 : 1][CP];  // coarse sums of the plane pair
     // coarse level (restriction): column byte offsets, dropped where the pair is not owned
     uint32_t cco[CP];
@@ -573,7 +724,7 @@ struct Pass {
     double sumsq = 0.0, sumsq_b = 0.0;
     auto store = [&](int sp) {  // u_out from queue slot 0, r32 from RK
       const PlaneBuf bo = plane_buf(a.out, (size_t)sp * planeb, planeb);
-      if constexpr (MODE == kFvJacobi) {
+      if constexpr (JAC) {
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
           if (!rin[i]) continue;
@@ -595,11 +746,31 @@ struct Pass {
     };
 
     // prologue: planes z0-1, z0, z0+1 queued, the plane arrays of z0 taken, the edges of
-    // plane z0 written for the first step
+    // plane z0 written for the first step.
+    // Prolongation: the correction reaches plane q+1 of the queue at the start of step q
+    // (after the loads of the step are issued, so that it overlaps their latency) and plane
+    // q's halo column and row in step q.  Step q therefore reads the coarse planes
+    // floor(q/2) .. floor((q+1)/2) + 1: coarse plane Z is first read in step 2Z-3 and last
+    // in step 2Z+1, so it is staged in step 2Z-4 (even steps: one plane each) into the slot
+    // of plane Z-3, last read in step 2Z-5.  With z0 = 2 Z0 - 1 (odd) the prologue stages
+    // Z0-1 .. Z0+1 and loads Z0+2 (staged in step z0+1).
+    if constexpr (PRO) {
+      const int Z0 = (z0 + 1) / 2;
+      cload(Z0 - 1, CR);
+      cstore(Z0 - 1, CR);
+      cload(Z0, CR);
+      cstore(Z0, CR);
+      cload(Z0 + 1, CR);
+      cstore(Z0 + 1, CR);
+      cload(Z0 + 2, CR);
+      __syncthreads();
+    }
     load_q(z0 - 1);
     shift_in(z0 - 1);
+    if constexpr (PRO) prolong_in(z0 - 1);
     load_q(z0);
     shift_in(z0);
+    if constexpr (PRO) prolong_in(z0);
     load_q(z0 + 1);
     shift_in(z0 + 1);
     load_c(z0);
@@ -610,10 +781,20 @@ struct Pass {
       constexpr int bb = decltype(BC)::value;
       constexpr int rb = 1 - bb, wb = bb;  // LDS buffer written in the previous / this step
       __syncthreads();
-      if ((REFINE || MODE == kFvJacobi) && s > z0) store(s - 1);
+      if constexpr (PRO) {
+        if (bb == 1) {  // even step s: stage coarse plane s/2 + 2, load the next one
+          cstore(s / 2 + 2, CR);
+          cload(s / 2 + 3, CR);
+        }
+      }
+      if ((REFINE || JAC) && s > z0) store(s - 1);
       const bool gzm = s == 1, gzp = s + 1 == n - 1;
       if (s + 2 <= z1) load_q(s + 2);
       if (s + 1 < z1) load_c(s + 1);
+      if constexpr (PRO) {
+        prolong_in(s + 1);  // the edges of plane s+1 are written at the end of this step
+        prolong_halo(s);
+      }
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
 #pragma unroll
@@ -682,7 +863,7 @@ struct Pass {
               if (own) sumsq_b += bv * bv;
             }
             if constexpr (REFINE) RK[i][p][o] = own ? (float)(r * a.inv_scale) : 0.0f;
-            if constexpr (MODE == kFvJacobi) JV[i][p][o] = ui + a.coef * r;
+            if constexpr (JAC) JV[i][p][o] = ui + a.coef * r;
             if constexpr (MODE == kFvRestrict) {
               // steps of parity 0 are the odd (first) planes of a coarse cell's children
               if (bb == 0 && i % 2 == 0 && o == 0) RA[i / 2][p] = 0.0;
@@ -715,8 +896,8 @@ struct Pass {
       stepfn(IC<1>{}, s);
       ++s;
     }
-    if (REFINE || MODE == kFvJacobi) store(z1 - 1);  // queue slot 0 holds plane z1-1
-    if constexpr (MODE == kFvJacobi || MODE == kFvRestrict) return;  // no norm
+    if (REFINE || JAC) store(z1 - 1);  // queue slot 0 holds plane z1-1
+    if constexpr (JAC || MODE == kFvRestrict) return;  // no norm
 
 #pragma unroll
     for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
@@ -972,28 +1153,32 @@ void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double
 
 namespace {
 // Shape of the finite-volume passes: the norm and refinement shape, 256-column tiles from
-// N = 256 on (two per row at N = 512), 128 columns below.
+// N = 256 on (two per row at N = 512), 128 columns below; the sweep with the prolongation
+// has a shape of its own.
 template <int MODE, typename Fill>
 void launch_fv(hipStream_t s, int N, double* partial, double* out, Fill fill)
 {
+  constexpr bool PRO = MODE == kFvJacobiProlong;
+  constexpr int W = PRO ? MG_FV_PROLONG_W : MG_PASS_W, RPW = PRO ? MG_FV_PROLONG_RPW : MG_PASS_RPW;
   auto go = [&](auto cpc) {
     constexpr int CP = decltype(cpc)::value;
-    using C = Pass<false, MODE, MG_PASS_W, MG_PASS_RPW, CP>;
-    auto kern = k_pass<false, MODE, MG_PASS_W, MG_PASS_RPW, CP>;
+    using C = Pass<false, MODE, W, RPW, CP>;
+    auto kern = k_pass<false, MODE, W, RPW, CP>;
     typename C::Args a{};
     fill(a);
     a.n = N + 2;
     a.tiles_x = (N + C::BX - 1) / C::BX;
     a.tiles_y = (N + C::BY - 1) / C::BY;
     const int per = a.tiles_x * a.tiles_y;
-    a.zlen = best_zlen(per, N, 2, capacity_of(kern, 64 * MG_PASS_W), kStreamPartials);
-    if (MODE == kFvRestrict) a.zlen += a.zlen & 1;  // chunks start on odd planes
+    a.zlen = best_zlen(per, N, 2, capacity_of(kern, 64 * W), kStreamPartials);
+    // chunks start on odd planes
+    if (MODE == kFvRestrict || MODE == kFvJacobiProlong) a.zlen += a.zlen & 1;
     const int blocks = per * ((N + a.zlen - 1) / a.zlen);
     a.partial = partial;
-    kern<<<blocks, 64 * MG_PASS_W, 0, s>>>(a);
+    kern<<<blocks, 64 * W, 0, s>>>(a);
     if (MODE == kFvNorm) k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
   };
-  if (N > 128) go(IC<2>{});
+  if (N > 128) go(IC<MODE == kFvJacobiProlong ? MG_FV_PROLONG_CP : 2>{});
   else go(IC<1>{});
 }
 }  // namespace
@@ -1005,6 +1190,15 @@ void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double*
 {
   launch_fv<kFvJacobi>(s, N, partial, nullptr, [&](auto& a) {
     a.f = f; a.u = u; a.out = uout; a.ih2 = 1.0 / (h * h); a.coef = omega * (h * h / 6.0);
+  });
+}
+
+void fv_jacobi_prolong_tiled(hipStream_t s, int N, double h, double omega, const double* f,
+                             const double* u, const double* ec, double* uout, double* partial)
+{
+  launch_fv<kFvJacobiProlong>(s, N, partial, nullptr, [&](auto& a) {
+    a.f = f; a.u = u; a.ec = ec; a.out = uout; a.ih2 = 1.0 / (h * h);
+    a.coef = omega * (h * h / 6.0);
   });
 }
 
