@@ -154,10 +154,13 @@ mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, doubl
  *  MG_FUSE_BLOCKED  temporally blocked out-of-place smoother and single-pass streaming
  *                   residual / restriction / norm / refinement kernels on large 3D levels
  *                   (otherwise the per-colour smoother and one launch per step);
- *  MG_FUSE_PROLONG  on such levels, the coarse-grid correction u += P e applied inside the
- *                   first post-smoothing pass (FP32 passes) instead of a separate pass;
- *  MG_FUSE_ZERO     a zero initial guess read as 0 by the first pre-smoothing pass instead
- *                   of being written first;
+ *  MG_FUSE_PROLONG  the coarse-grid correction u += P e applied inside the first
+ *                   post-smoothing pass (blocked levels: FP32 passes) or, on levels served
+ *                   by the per-colour kernels, inside the first colour-0 half-sweep, instead
+ *                   of a separate pass;
+ *  MG_FUSE_ZERO     a zero initial guess read as 0 by the first pre-smoothing pass (or the
+ *                   first colour-0 half-sweep, which also writes the other colour's zeros)
+ *                   instead of being written first;
  *  MG_FUSE_TAIL     all levels with at most 4096 interior nodes in one launch;
  *  MG_FUSE_RESTRICT on such large 3D levels, the residual and its full-weighting restriction
  *                   computed inside the pre-smoothing pass (FP32 passes from a zero guess,

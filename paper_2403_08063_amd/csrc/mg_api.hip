@@ -210,8 +210,9 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
 {
   const Level& L = c->lv[l];
   const int dim = c->g.dim;
-  if (ec && (sweeps == 0 || !use_tiled(c, l) || !(c->fuse & MG_FUSE_PROLONG) ||
-             !mgk::rbgs_tiled_fuses_prolong(sizeof(T)))) {
+  const bool tiled = use_tiled(c, l);
+  if (ec && (sweeps == 0 || !(c->fuse & MG_FUSE_PROLONG) ||
+             (tiled && !mgk::rbgs_tiled_fuses_prolong(sizeof(T))))) {
     // coarse-grid correction as a separate pass when it cannot ride on a fused sweep
     mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, u);
     ec = nullptr;
@@ -220,11 +221,11 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
     if (zero_guess) mgk::fill<T>(c->s, L.N, T(0), u);
     return u;
   }
-  if (use_tiled(c, l)) {
-    if (zero_guess && !(c->fuse & MG_FUSE_ZERO)) {
-      mgk::fill<T>(c->s, L.N, T(0), u);
-      zero_guess = false;
-    }
+  if (zero_guess && !(c->fuse & MG_FUSE_ZERO)) {
+    mgk::fill<T>(c->s, L.N, T(0), u);
+    zero_guess = false;
+  }
+  if (tiled) {
     T* cur = u;
     T* other = t;
     int left = sweeps;
@@ -243,9 +244,11 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
     }
     return cur;
   }
-  if (zero_guess) mgk::fill<T>(c->s, L.N, T(0), u);
+  // per-colour kernels; the zero guess or the coarse-grid correction rides on the first
+  // colour-0 half-sweep (the boundary of a zero-guess level, a coarse level, is 0)
   for (int s = 0; s < sweeps; ++s) {
-    mgk::rbgs_colour<T>(c->s, dim, L.n, L.h, k, f, u, 0);
+    if (s == 0 && (zero_guess || ec)) mgk::rbgs_first<T>(c->s, dim, L.n, L.h, k, f, u, ec);
+    else mgk::rbgs_colour<T>(c->s, dim, L.n, L.h, k, f, u, 0);
     mgk::rbgs_colour<T>(c->s, dim, L.n, L.h, k, f, u, 1);
   }
   return u;

@@ -17,6 +17,16 @@ template <typename T>
 void rbgs_colour(hipStream_t s, int dim, int n, double h, const T* k, const T* f, T* u,
                  int colour);
 
+// The first colour-0 half-sweep of a smoothing, in place: ec == nullptr: from a zero guess
+// (colour-0 nodes get the Gauss-Seidel value of the zero iterate, colour-1 nodes are set to
+// 0; boundary nodes must already be 0); ec != nullptr: of u + P ec (ec on the next coarser
+// level), the correction read on the fly and not stored -- valid as the first half-sweep of
+// a full sweep, whose colour-1 half-sweep overwrites every colour-1 node.  Bitwise equal to
+// the fill or prolong_add followed by rbgs_colour(.., 0).
+template <typename T>
+void rbgs_first(hipStream_t s, int dim, int n, double h, const T* k, const T* f, T* u,
+                const T* ec);
+
 // `sweeps` (1 or 2) full red-black sweeps fused in one pass over a 3D level, out of place:
 // uout = RBGS^sweeps(uin).  zero_in: treat uin as identically 0 (not read).  ec != nullptr:
 // the input is uin + P ec (coarse-grid correction with (n-1)/2+1 nodes per side, added on

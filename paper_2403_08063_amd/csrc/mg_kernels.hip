@@ -34,6 +34,55 @@ __global__ void __launch_bounds__(kBlock)
   u[i] = gs_at<T, DIM, VAR>(f, u, k, i, sy, sz, h2);
 }
 
+// The first colour-0 half-sweep of a pre-smoothing from a zero guess: colour-0 nodes take
+// the Gauss-Seidel value of the zero iterate, colour-1 nodes are set to 0 (the fill of the
+// zero guess, in the same launch; boundary nodes, 0 on the coarse levels, are not written).
+template <typename T, int DIM, bool VAR>
+__global__ void __launch_bounds__(kBlock)
+    k_rbgs_first_zero(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ k,
+                      int n, T h2)
+{
+  const int y = blockIdx.y + 1;
+  const int z = DIM == 3 ? (int)blockIdx.z + 1 : 0;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int x0 = 1 + ((1 + y + z) & 1) + 2 * q, x1 = 1 + ((y + z) & 1) + 2 * q;
+  const size_t sy = (size_t)n, sz = (size_t)n * n;
+  const size_t row = ((size_t)z * n + y) * (size_t)n;
+  if (x0 <= n - 2) u[row + x0] = gs_zero_at<T, DIM, VAR>(f, k, row + x0, sy, sz, h2);
+  if (x1 <= n - 2) u[row + x1] = T(0);
+}
+
+// The first colour-0 half-sweep of a post-smoothing with the coarse-grid correction: the
+// colour-1 neighbours are read as u + P ec (corrected_at), so the correction is never
+// stored -- the colour-0 nodes are overwritten by this half-sweep and the colour-1 nodes by
+// the next, neither reading its own old value.
+template <typename T, int DIM, bool VAR>
+__global__ void __launch_bounds__(kBlock)
+    k_rbgs_first_prolong(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ k,
+                         const T* __restrict__ ec, int n, int nc, T h2)
+{
+  const int y = blockIdx.y + 1;
+  const int z = DIM == 3 ? (int)blockIdx.z + 1 : 0;
+  const int x = 1 + ((1 + y + z) & 1) + 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (x > n - 2) return;
+  const size_t sy = (size_t)n, sz = (size_t)n * n;
+  const size_t i = ((size_t)z * n + y) * (size_t)n + x;
+  const T xm = corrected_at<T, DIM>(u, ec, n, nc, z, y, x - 1);
+  const T xp = corrected_at<T, DIM>(u, ec, n, nc, z, y, x + 1);
+  const T ym = corrected_at<T, DIM>(u, ec, n, nc, z, y - 1, x);
+  const T yp = corrected_at<T, DIM>(u, ec, n, nc, z, y + 1, x);
+  const T zm = DIM == 3 ? corrected_at<T, DIM>(u, ec, n, nc, z - 1, y, x) : T(0);
+  const T zp = DIM == 3 ? corrected_at<T, DIM>(u, ec, n, nc, z + 1, y, x) : T(0);
+  const T h2f = h2 * f[i];
+  if (!VAR) {
+    u[i] = gs_const<T, DIM>(h2f, xm, xp, ym, yp, zm, zp);
+  } else {
+    const T kzm = DIM == 3 ? k[i - sz] : T(0), kzp = DIM == 3 ? k[i + sz] : T(0);
+    u[i] = gs_var<T, DIM>(h2f, k[i], xm, k[i - 1], xp, k[i + 1], ym, k[i - sy], yp, k[i + sy],
+                          zm, kzm, zp, kzp);
+  }
+}
+
 // ------------------------------------------------------------------ residual
 template <typename T, int DIM, bool VAR>
 __global__ void __launch_bounds__(kBlock)
@@ -486,6 +535,34 @@ void rbgs_colour(hipStream_t s, int dim, int n, double h, const T* k, const T* f
 }
 
 template <typename T>
+void rbgs_first(hipStream_t s, int dim, int n, double h, const T* k, const T* f, T* u,
+                const T* ec)
+{
+  const int half = (n - 1) / 2;
+  const int bx = half >= 256 ? 256 : (half > 64 ? 128 : 64);
+  const dim3 grid(cdiv(half, bx), n - 2, dim == 3 ? n - 2 : 1);
+  const T h2 = (T)(h * h);
+  const int nc = (n - 1) / 2 + 1;
+  if (ec) {
+    if (dim == 3) {
+      if (k) k_rbgs_first_prolong<T, 3, true><<<grid, bx, 0, s>>>(u, f, k, ec, n, nc, h2);
+      else k_rbgs_first_prolong<T, 3, false><<<grid, bx, 0, s>>>(u, f, k, ec, n, nc, h2);
+    } else {
+      if (k) k_rbgs_first_prolong<T, 2, true><<<grid, bx, 0, s>>>(u, f, k, ec, n, nc, h2);
+      else k_rbgs_first_prolong<T, 2, false><<<grid, bx, 0, s>>>(u, f, k, ec, n, nc, h2);
+    }
+  } else {
+    if (dim == 3) {
+      if (k) k_rbgs_first_zero<T, 3, true><<<grid, bx, 0, s>>>(u, f, k, n, h2);
+      else k_rbgs_first_zero<T, 3, false><<<grid, bx, 0, s>>>(u, f, k, n, h2);
+    } else {
+      if (k) k_rbgs_first_zero<T, 2, true><<<grid, bx, 0, s>>>(u, f, k, n, h2);
+      else k_rbgs_first_zero<T, 2, false><<<grid, bx, 0, s>>>(u, f, k, n, h2);
+    }
+  }
+}
+
+template <typename T>
 void residual(hipStream_t s, int dim, int n, double h, const T* k, const T* f, const T* u, T* r)
 {
   const int bx = n >= 256 ? 256 : 64;
@@ -632,6 +709,8 @@ void zero_boundary(hipStream_t s, int dim, int n, double* p)
 // explicit instantiations
 template void rbgs_colour<double>(hipStream_t, int, int, double, const double*, const double*, double*, int);
 template void rbgs_colour<float>(hipStream_t, int, int, double, const float*, const float*, float*, int);
+template void rbgs_first<double>(hipStream_t, int, int, double, const double*, const double*, double*, const double*);
+template void rbgs_first<float>(hipStream_t, int, int, double, const float*, const float*, float*, const float*);
 template void residual<double>(hipStream_t, int, int, double, const double*, const double*, const double*, double*);
 template void residual<float>(hipStream_t, int, int, double, const float*, const float*, const float*, float*);
 template void restrict_residual<double>(hipStream_t, int, int, double, const double*, const double*, const double*, double*);

@@ -121,6 +121,18 @@ __device__ __forceinline__ T gs_at(const T* __restrict__ f, const T* u, const T*
                         zm, kzm, zp, kzp);
 }
 
+// Gauss-Seidel value at interior node i of a zero iterate: gs_at with every neighbour 0.
+template <typename T, int DIM, bool VAR>
+__device__ __forceinline__ T gs_zero_at(const T* __restrict__ f, const T* __restrict__ k,
+                                        size_t i, size_t sy, size_t sz, T h2)
+{
+  const T h2f = h2 * f[i];
+  if (!VAR) return gs_const<T, DIM>(h2f, T(0), T(0), T(0), T(0), T(0), T(0));
+  const T kzm = DIM == 3 ? k[i - sz] : T(0), kzp = DIM == 3 ? k[i + sz] : T(0);
+  return gs_var<T, DIM>(h2f, k[i], T(0), k[i - 1], T(0), k[i + 1], T(0), k[i - sy], T(0),
+                        k[i + sy], T(0), kzm, T(0), kzp);
+}
+
 // Full weighting of the fine residual around coarse interior node (X, Y, Z): the 3^d fine
 // residuals around 2I combined with weights prod_a w(o_a), w(0) = 1/2, w(+-1) = 1/4, summed
 // in the loop order z, y, x.
@@ -167,6 +179,34 @@ __device__ __forceinline__ void prolong_pair(const T* __restrict__ e, T* __restr
   const size_t i = ((size_t)z * nf + y) * (size_t)nf + (2 * c - 1);
   u[i] = u[i] + sodd;
   if (2 * c <= nf - 2) u[i + 1] = u[i + 1] + seven;
+}
+
+// u + P e at fine node (z, y, x) of a level with nf nodes per side (boundary nodes: u): the
+// terms prolong_pair adds to that node, in its order.
+template <typename T, int DIM>
+__device__ __forceinline__ T corrected_at(const T* u, const T* __restrict__ e, int nf, int nc,
+                                          int z, int y, int x)
+{
+  const size_t i = ((size_t)z * nf + y) * (size_t)nf + x;
+  if (x < 1 || x > nf - 2 || y < 1 || y > nf - 2 || (DIM == 3 && (z < 1 || z > nf - 2)))
+    return u[i];
+  const int mz = DIM == 3 ? 1 + (z & 1) : 1, my = 1 + (y & 1);
+  const int cz0 = DIM == 3 ? z >> 1 : 0, cy0 = y >> 1;
+  const T wz = DIM == 3 ? ((z & 1) ? T(0.5) : T(1)) : T(1);
+  const T wy = (y & 1) ? T(0.5) : T(1);
+  const int c = (x + 1) >> 1;  // x = 2c-1 (odd) or 2c (even)
+  T s = T(0);
+  for (int a = 0; a < mz; ++a)
+    for (int b = 0; b < my; ++b) {
+      const size_t row = ((size_t)(cz0 + a) * nc + (cy0 + b)) * (size_t)nc;
+      if (x & 1) {
+        s = s + (wz * wy * T(0.5)) * e[row + c - 1];
+        s = s + (wz * wy * T(0.5)) * e[row + c];
+      } else {
+        s = s + (wz * wy * T(1)) * e[row + c];
+      }
+    }
+  return u[i] + s;
 }
 
 // Interior unknown q of a level with n nodes per side <-> node (z, y, x), lexicographic.

@@ -119,20 +119,24 @@ def test_coarse_tail_bitwise_equals_per_level_launches(dim, n, levels, var, prec
 
 @pytest.mark.parametrize("off", ["prolong", "zero", "restrict"])
 @pytest.mark.parametrize("prec", ["f64", "f32_ir"])
-@pytest.mark.parametrize("n,levels,var", [(161, 6, False), (321, 7, False), (161, 6, True)])
-def test_fused_passes_bitwise_equal_separate_passes(n, levels, var, prec, off):
+@pytest.mark.parametrize("dim,n,levels,var", [(3, 161, 6, False), (3, 321, 7, False),
+                                               (3, 161, 6, True), (2, 257, 7, True),
+                                               (2, 129, 6, False)])
+def test_fused_passes_bitwise_equal_separate_passes(dim, n, levels, var, prec, off):
     """On levels served by the blocked smoother, the coarse-grid correction added inside the
     first post-smoothing pass, a zero initial guess read as 0 by the first pre-smoothing pass
     and the residual restriction computed inside that pass reproduce the separate
     prolongation, fill and restriction passes bit for bit (at 321^3 the second level,
-    161^3, takes the zero-guess pass in FP64 as well)."""
-    say(f"fused passes n={n} var={var} prec={prec} off={off}")
-    k = random_k(3, n, 32) if var else None
-    f = dev(inputs.uniform_interior(3, n, 31))
+    161^3, takes the zero-guess pass in FP64 as well).  On the levels of the per-colour
+    kernels (41^3 and 21^3 below 161^3, every 2D level above the coarse tail) the correction
+    and the zero guess ride on the first colour-0 half-sweep instead, equally bit for bit."""
+    say(f"fused passes dim={dim} n={n} var={var} prec={prec} off={off}")
+    k = random_k(dim, n, 32) if var else None
+    f = dev(inputs.uniform_interior(dim, n, 31))
     out = []
     drop = {"prolong": FUSE_PROLONG, "zero": FUSE_ZERO, "restrict": FUSE_RESTRICT}[off]
     for flags in (FUSE_ALL, FUSE_ALL & ~drop):
-        mg = Multigrid(3, n, levels, variable=var, precision=prec, device=DEV)
+        mg = Multigrid(dim, n, levels, variable=var, precision=prec, device=DEV)
         mg.set_fusion(flags)
         if var:
             mg.set_coefficients(dev(k))
