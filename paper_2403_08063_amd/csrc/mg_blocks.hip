@@ -356,7 +356,7 @@ __device__ __forceinline__ void fill_ghost(int B, int order, const C2FWeights& W
 __global__ void __launch_bounds__(kFillThreads)
     k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
 {
-  const int q = blockIdx.x * kFillThreads + threadIdx.x;  // ghost cell of the face
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // ghost cell of the face
   if (q >= B * B) return;
   fill_ghost(B, order, W, faces, u, q, blockIdx.y, blockIdx.z);
 }
@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(kFillThreads)
     k_blk_copy_boundary(int B, const int* __restrict__ faces, const double* __restrict__ src,
                         double* __restrict__ dst)
 {
-  const int q = blockIdx.x * kFillThreads + threadIdx.x;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= B * B) return;
   const int f = blockIdx.y, b = blockIdx.z;
   if (faces[((size_t)b * 6 + f) * kFaceInts] != kFaceBoundary) return;
@@ -747,18 +747,25 @@ __global__ void __launch_bounds__(kFillThreads)
 }
 
 // ---------------------------------------------------------------- host drivers
-dim3 face_grid(int B) { return dim3((unsigned)((B * B + kFillThreads - 1) / kFillThreads), 6, kBlocks); }
+// one workgroup per (face, block) and up to kFillThreads ghost cells of the face; faces of
+// at most 64 cells (B <= 8) take one wave, not a workgroup of mostly idle waves
+int face_threads(int B) { return B * B <= 64 ? 64 : kFillThreads; }
+dim3 face_grid(int B)
+{
+  const int t = face_threads(B);
+  return dim3((unsigned)((B * B + t - 1) / t), 6, kBlocks);
+}
 
 void fill(mgblk_ctx* c, int l, double* u)
 {
   const int B = c->lv[l].B;
-  k_blk_fill<<<face_grid(B), kFillThreads, 0, c->s>>>(B, c->g.order, c->w, c->faces, u);
+  k_blk_fill<<<face_grid(B), face_threads(B), 0, c->s>>>(B, c->g.order, c->w, c->faces, u);
 }
 
 void copy_boundary(mgblk_ctx* c, int l, const double* src, double* dst)
 {
   const int B = c->lv[l].B;
-  k_blk_copy_boundary<<<face_grid(B), kFillThreads, 0, c->s>>>(B, c->faces, src, dst);
+  k_blk_copy_boundary<<<face_grid(B), face_threads(B), 0, c->s>>>(B, c->faces, src, dst);
 }
 
 // `count` sweeps on level l with a fill before each, alternating between cur and oth (which
