@@ -155,7 +155,8 @@ mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, doubl
  *                   residual / restriction / norm / refinement kernels on large 3D levels
  *                   (otherwise the per-colour smoother and one launch per step);
  *  MG_FUSE_PROLONG  the coarse-grid correction u += P e applied inside the first
- *                   post-smoothing pass (blocked levels: FP32 passes) or, on levels served
+ *                   post-smoothing pass (blocked levels: FP32 passes and the FP64
+ *                   constant-coefficient pass) or, on levels served
  *                   by the per-colour kernels, inside the first colour-0 half-sweep, instead
  *                   of a separate pass;
  *  MG_FUSE_ZERO     a zero initial guess read as 0 by the first pre-smoothing pass (or the

@@ -212,7 +212,7 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
   const int dim = c->g.dim;
   const bool tiled = use_tiled(c, l);
   if (ec && (sweeps == 0 || !(c->fuse & MG_FUSE_PROLONG) ||
-             (tiled && !mgk::rbgs_tiled_fuses_prolong(sizeof(T))))) {
+             (tiled && !mgk::rbgs_tiled_fuses_prolong(sizeof(T), k != nullptr)))) {
     // coarse-grid correction as a separate pass when it cannot ride on a fused sweep
     mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, u);
     ec = nullptr;

@@ -42,7 +42,7 @@ void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T*
 // sweeps one pass may fuse.
 bool rbgs_tiled_supported(int dim, int n);
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes);
-bool rbgs_tiled_fuses_prolong(size_t value_bytes);
+bool rbgs_tiled_fuses_prolong(size_t value_bytes, bool var);
 bool rbgs_tiled_fuses_restrict(size_t value_bytes, bool var);
 
 // r = f - A u (interior), 0 on the boundary.

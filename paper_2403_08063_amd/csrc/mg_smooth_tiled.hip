@@ -634,15 +634,27 @@ LaunchShape shape_for(int n, int capacity)
 #ifndef MG_SMOOTH32_PROLONG_NARROW
 #define MG_SMOOTH32_PROLONG_NARROW 1
 #endif
+// The FP64 post-smoothing pass with the prolongation holds the coarse correction's planes
+// as well: 10 waves of 2 rows (64 x 40-node tiles in the 64-column layout) keep it within
+// 152 VGPRs; 8 x 4 spills.  Timed inside the FP64 solve at 513^3 (29.0 ms against 29.3 for
+// 12 x 2, 29.8 for 8 x 2 with a second prefetch buffer and 32.3 with the separate pass).
+#ifndef MG_SMOOTH64_PROLONG_W
+#define MG_SMOOTH64_PROLONG_W 10
+#endif
+#ifndef MG_SMOOTH64_PROLONG_RPW
+#define MG_SMOOTH64_PROLONG_RPW 2
+#endif
 template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
   static constexpr int W = RES                ? MG_SMOOTH32_RES_W
+                           : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_W
                            : !(f32 && plain)   ? MG_SMOOTH_W
                            : IN == kInProlong ? MG_SMOOTH32_PROLONG_W
                            : IN == kInZero    ? MG_SMOOTH32_ZERO_W
                                               : MG_SMOOTH32_READ_W;
   static constexpr int RPW = RES                ? MG_SMOOTH32_RES_RPW
+                             : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_RPW
                              : !(f32 && plain)   ? MG_SMOOTH_RPW
                              : IN == kInProlong ? MG_SMOOTH32_PROLONG_RPW
                              : IN == kInRead    ? MG_SMOOTH32_READ_RPW
@@ -694,8 +706,9 @@ void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T*
                 bool zero_in, const T* ec)
 {
   if (ec) {
-    // only FP32 passes fuse the prolongation (rbgs_tiled_fuses_prolong)
-    if constexpr (sizeof(T) == 4) launch_in<T, VAR, S, kInProlong>(s, n, h, k, f, uin, uout, ec);
+    // FP32 passes and the plain FP64 pass fuse the prolongation (rbgs_tiled_fuses_prolong)
+    if constexpr (sizeof(T) == 4 || (!VAR && S == 2))
+      launch_in<T, VAR, S, kInProlong>(s, n, h, k, f, uin, uout, ec);
   } else if (zero_in) launch_in<T, VAR, S, kInZero>(s, n, h, k, f, uin, uout, ec);
   else launch_in<T, VAR, S, kInRead>(s, n, h, k, f, uin, uout, ec);
 }
@@ -710,10 +723,11 @@ void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T*
 #endif
 bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n > MG_TILED_MIN_N; }
 
-bool rbgs_tiled_fuses_prolong(size_t value_bytes)
+bool rbgs_tiled_fuses_prolong(size_t value_bytes, bool var)
 {
-  // FP64 passes holding the coarse-grid correction as well exceed the register file
-  return value_bytes == 4;
+  // the FP64 variable-coefficient pass (one sweep, k in registers) has no registers left
+  // for the coarse-grid correction
+  return value_bytes == 4 || !var;
 }
 
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
