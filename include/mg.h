@@ -164,8 +164,8 @@ mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, doubl
  *                   instead of being written first;
  *  MG_FUSE_TAIL     all levels with at most 4096 interior nodes in one launch;
  *  MG_FUSE_RESTRICT on such large 3D levels, the residual and its full-weighting restriction
- *                   computed inside the pre-smoothing pass (FP32 passes from a zero guess,
- *                   constant coefficient) instead of a separate pass.
+ *                   computed inside the pre-smoothing pass (constant coefficient, FP32
+ *                   and FP64) instead of a separate pass.
  * Default MG_FUSE_ALL.  Clearing MG_FUSE_PROLONG, MG_FUSE_ZERO, MG_FUSE_TAIL or
  * MG_FUSE_RESTRICT leaves every result bitwise unchanged; without MG_FUSE_BLOCKED smoothing results are unchanged but
  * residual sums are accumulated in another order.  EINVAL for bits outside MG_FUSE_ALL. */

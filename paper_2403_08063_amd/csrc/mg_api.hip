@@ -282,10 +282,9 @@ T* cycle(mg_ctx* c, int l, T* u, T* t, const T* f, bool zero_guess)
     return u;
   }
   const View<T> C = view<T>(c, l + 1);
-  // residual + restriction inside the pre-smoothing pass: one FP32 2-sweep pass from a zero
-  // guess with constant coefficients (rbgs_tiled_fuses_restrict)
-  const bool fuse_r = use_tiled(c, l) && (c->fuse & MG_FUSE_RESTRICT) &&
-                      (c->fuse & MG_FUSE_ZERO) && zero_guess && c->g.nu1 == 2 &&
+  // residual + restriction inside the pre-smoothing pass: one 2-sweep pass with constant
+  // coefficients (rbgs_tiled_fuses_restrict)
+  const bool fuse_r = use_tiled(c, l) && (c->fuse & MG_FUSE_RESTRICT) && c->g.nu1 == 2 &&
                       mgk::rbgs_tiled_max_sweeps(V.k != nullptr, sizeof(T)) == 2 &&
                       mgk::rbgs_tiled_fuses_restrict(sizeof(T), V.k != nullptr);
   T* cur = smooth<T>(c, l, u, t, f, V.k, c->g.nu1, zero_guess, nullptr, fuse_r ? C.f : nullptr);

@@ -30,8 +30,8 @@ void rbgs_first(hipStream_t s, int dim, int n, double h, const T* k, const T* f,
 // `sweeps` (1 or 2) full red-black sweeps fused in one pass over a 3D level, out of place:
 // uout = RBGS^sweeps(uin).  zero_in: treat uin as identically 0 (not read).  ec != nullptr:
 // the input is uin + P ec (coarse-grid correction with (n-1)/2+1 nodes per side, added on
-// interior nodes as prolong_add does).  fc != nullptr (2 sweeps from a zero guess, FP32,
-// constant coefficient: rbgs_tiled_fuses_restrict): the pass also writes the full-weighting
+// interior nodes as prolong_add does).  fc != nullptr (2 sweeps, constant coefficient:
+// rbgs_tiled_fuses_restrict): the pass also writes the full-weighting
 // restriction of the residual f - A uout to the interior of fc, the next coarser level's
 // right-hand side, with the arithmetic of restrict_residual_tiled.  The boundary of uout
 // (and of fc) is not written.

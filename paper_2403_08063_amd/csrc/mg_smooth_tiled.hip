@@ -638,6 +638,16 @@ LaunchShape shape_for(int n, int capacity)
 // as well: 10 waves of 2 rows (64 x 40-node tiles in the 64-column layout) keep it within
 // 152 VGPRs; 8 x 4 spills.  Timed inside the FP64 solve at 513^3 (29.0 ms against 29.3 for
 // 12 x 2, 29.8 for 8 x 2 with a second prefetch buffer and 32.3 with the separate pass).
+// The FP64 pre-smoothing pass with the residual restriction holds two more planes: 8 waves
+// of 2 rows (64 x 32-node tiles) fit in 200-208 VGPRs; 10 x 2 and 8 x 4 spill, 12 x 2
+// exceeds the LDS.  FP64 solve at 513^3: 27.3 ms against 29.0 with the separate
+// restriction pass.
+#ifndef MG_SMOOTH64_RES_W
+#define MG_SMOOTH64_RES_W 8
+#endif
+#ifndef MG_SMOOTH64_RES_RPW
+#define MG_SMOOTH64_RES_RPW 2
+#endif
 #ifndef MG_SMOOTH64_PROLONG_W
 #define MG_SMOOTH64_PROLONG_W 10
 #endif
@@ -647,19 +657,19 @@ LaunchShape shape_for(int n, int capacity)
 template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
-  static constexpr int W = RES                ? MG_SMOOTH32_RES_W
+  static constexpr int W = RES                ? (f32 ? MG_SMOOTH32_RES_W : MG_SMOOTH64_RES_W)
                            : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_W
                            : !(f32 && plain)   ? MG_SMOOTH_W
                            : IN == kInProlong ? MG_SMOOTH32_PROLONG_W
                            : IN == kInZero    ? MG_SMOOTH32_ZERO_W
                                               : MG_SMOOTH32_READ_W;
-  static constexpr int RPW = RES                ? MG_SMOOTH32_RES_RPW
+  static constexpr int RPW = RES                ? (f32 ? MG_SMOOTH32_RES_RPW : MG_SMOOTH64_RES_RPW)
                              : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_RPW
                              : !(f32 && plain)   ? MG_SMOOTH_RPW
                              : IN == kInProlong ? MG_SMOOTH32_PROLONG_RPW
                              : IN == kInRead    ? MG_SMOOTH32_READ_RPW
                                                 : MG_SMOOTH_RPW;
-  static constexpr int PD = RES ? MG_SMOOTH32_RES_PD
+  static constexpr int PD = RES ? (f32 ? MG_SMOOTH32_RES_PD : 1)
                             : !plain ? 1
                             : IN == kInProlong ? (f32 ? MG_SMOOTH32_PROLONG_PD : 1)
                             : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
@@ -739,8 +749,7 @@ int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
 
 bool rbgs_tiled_fuses_restrict(size_t value_bytes, bool var)
 {
-  // the FP64 pass holding two more planes exceeds the register file
-  return value_bytes == 4 && !var;
+  return !var;
 }
 
 template <typename T>
@@ -748,13 +757,12 @@ void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T*
                 int sweeps, bool zero_in, const T* ec, T* fc)
 {
   if (fc) {
-    // two sweeps from a zero guess with the residual restricted into fc; the host asks for
-    // it only where rbgs_tiled_fuses_restrict holds
-    if constexpr (sizeof(T) == 4) {
-      if (!k && sweeps == 2 && zero_in && !ec) {
-        launch_in<T, false, 2, kInZero, 1>(s, n, h, k, f, uin, uout, ec, fc);
-        return;
-      }
+    // two sweeps with the residual restricted into fc; the host asks for it only where
+    // rbgs_tiled_fuses_restrict holds
+    if (!k && sweeps == 2 && !ec) {
+      if (zero_in) launch_in<T, false, 2, kInZero, 1>(s, n, h, k, f, uin, uout, ec, fc);
+      else launch_in<T, false, 2, kInRead, 1>(s, n, h, k, f, uin, uout, ec, fc);
+      return;
     }
   }
   // the host asks for 2 sweeps with k only in FP32 (rbgs_tiled_max_sweeps)
