@@ -497,16 +497,27 @@ mg_status solve_impl(mg_ctx* c, const double* f, double* u, double tol, int* cyc
   if (c->g.precision == MG_F32_IR && use_tiled(c, 0) && !c->g.variable && c->last_bn > 0)
     return solve_ir_streamed(c, f, u, tol, 0.0, cycles, relres);
   double bn2 = 0, rn2 = 0;
-  norm2(c, f, u, 1, 1);
-  if (mg_status st = launch_check(c, "norm")) return st;
-  if (mg_status st = read_scalar(c, c->scal + 1, &bn2)) return st;
+  const bool both = use_tiled(c, 0) && !c->g.variable && c->g.precision == MG_F64;
+  if (both) {
+    // residual and right-hand-side norms in one pass (each in its own pass's order)
+    mgk::resid_norm2_both_tiled(c->s, L0.n, L0.h, f, u, c->partial, c->partial_b, c->scal);
+    if (mg_status st = launch_check(c, "norm")) return st;
+    if (mg_status st = read_scalar(c, c->scal + 1, &bn2)) return st;
+    if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
+  } else {
+    norm2(c, f, u, 1, 1);
+    if (mg_status st = launch_check(c, "norm")) return st;
+    if (mg_status st = read_scalar(c, c->scal + 1, &bn2)) return st;
+  }
   double bn = std::sqrt(bn2);
   if (!(bn > 0)) bn = 1.0;
   if (c->g.precision == MG_F32_IR && use_tiled(c, 0))
     return solve_ir_streamed(c, f, u, tol, bn, cycles, relres);
-  norm2(c, f, u, 0, 0);
-  if (mg_status st = launch_check(c, "norm")) return st;
-  if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
+  if (!both) {
+    norm2(c, f, u, 0, 0);
+    if (mg_status st = launch_check(c, "norm")) return st;
+    if (mg_status st = read_scalar(c, c->scal, &rn2)) return st;
+  }
   double rn = std::sqrt(rn2);
   double rel = rn / bn;
   int k = 0;

@@ -63,6 +63,10 @@ void restrict_residual_tiled(hipStream_t s, int nf, double h, const T* k, const 
 // mode 0: ||f - A u||^2; mode 1: interior of u read as 0.  partial: kStreamPartials doubles.
 void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
                        const double* u, int mode, double* partial, double* out);
+// Both in one pass (constant coefficient): out[0] as mode 0, out[1] as mode 1, each summed
+// in the order of its own pass.  partial, partial_b: kStreamPartials doubles each.
+void resid_norm2_both_tiled(hipStream_t s, int n, double h, const double* f, const double* u,
+                            double* partial, double* partial_b, double* out);
 // Refinement pass: uout = u + scale * e on interior nodes (boundary of uout not written),
 // r = f - A uout, r32 = (float)(r * inv_scale), out[0] = sum of r^2 (interior).
 // partial_b (constant coefficient, e == nullptr: the first pass of a solve): also out[1] =

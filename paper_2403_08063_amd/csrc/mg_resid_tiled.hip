@@ -37,7 +37,7 @@ template <int V>
 using IC = std::integral_constant<int, V>;
 
 enum { kRestrict = 0, kNorm = 1, kRefine = 2, kFvNorm = 3, kFvJacobi = 4, kFvRestrict = 5,
-       kRefineRhs = 6, kFvJacobiProlong = 7 };
+       kRefineRhs = 6, kFvJacobiProlong = 7, kNormRhs = 8 };
 
 // Shape of the finite-volume sweep with the prolongation from N = 256 on (waves, rows per
 // wave, column pairs per lane), from timing sweeps on MI355X at 512^3 cells: 128 x 32-cell
@@ -361,7 +361,7 @@ struct Pass {
   // squares of the full right-hand side b = f - A u_B (u_B: the Dirichlet data of u with a
   // zero interior), with the operations of the norm pass reading the interior of u as 0
   static constexpr bool REFINE = MODE == kRefine || MODE == kRefineRhs;
-  static constexpr bool RHS = MODE == kRefineRhs;
+  static constexpr bool RHS = MODE == kRefineRhs || MODE == kNormRhs;  // kNormRhs: both norms
   static_assert(MODE != kFvRestrict || RPW % 2 == 0, "row pairs of the restriction");
   static_assert(!PRO || RPW % 2 == 0, "row pairs share their coarse parents");
   static_assert(!(FV && VAR), "the finite-volume scheme has a constant coefficient");
@@ -1083,14 +1083,16 @@ void launch_pass(hipStream_t s, typename Pass<VAR, MODE, W, RPW, CP>::Args a, do
   const int per = a.tiles_x * a.tiles_y;
   // the first refinement pass takes the norm pass's z-chunks, so that its right-hand-side
   // norm is summed in the norm pass's order
-  const int cap = MODE == kRefineRhs ? capacity_of(k_pass<VAR, kNorm, W, RPW, CP>, 64 * W)
-                                     : capacity_of(kern, 64 * W);
+  const int cap = (MODE == kRefineRhs || MODE == kNormRhs)
+                      ? capacity_of(k_pass<VAR, kNorm, W, RPW, CP>, 64 * W)
+                      : capacity_of(kern, 64 * W);
   a.zlen = best_zlen(per, m, 2, cap, kStreamPartials);
   const int blocks = per * ((m + a.zlen - 1) / a.zlen);
   a.partial = partial;
   kern<<<blocks, 64 * W, 0, s>>>(a);
   k_sum_fixed<<<1, 256, 0, s>>>(partial, blocks, out);
-  if (MODE == kRefineRhs) k_sum_fixed<<<1, 256, 0, s>>>(a.partial_b, blocks, out + 1);
+  if (MODE == kRefineRhs || MODE == kNormRhs)
+    k_sum_fixed<<<1, 256, 0, s>>>(a.partial_b, blocks, out + 1);
 }
 
 template <bool VAR, int MODE>
@@ -1126,6 +1128,14 @@ void resid_norm2_tiled(hipStream_t s, int n, double h, const double* k, const do
     fill(a);
     run_pass<false, kNorm>(s, a, partial, out);
   }
+}
+
+void resid_norm2_both_tiled(hipStream_t s, int n, double h, const double* f, const double* u,
+                            double* partial, double* partial_b, double* out)
+{
+  Pass<false, kNormRhs, 4, 2, 4>::Args a{};
+  a.f = f; a.u = u; a.n = n; a.ih2 = 1.0 / (h * h); a.partial_b = partial_b;
+  run_pass<false, kNormRhs>(s, a, partial, out);
 }
 
 void ir_pass_tiled(hipStream_t s, int n, double h, const double* k, const double* f,
