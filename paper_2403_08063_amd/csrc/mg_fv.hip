@@ -157,15 +157,16 @@ constexpr int kFvRowThreads = 128;
 
 dim3 grid3(int xs, int ys, int zs) { return dim3((unsigned)((xs + kFvRowThreads - 1) / kFvRowThreads), ys, zs); }
 
+// zero: u is identically 0, ghost layer included, and is not read (A u = +0)
 __global__ void __launch_bounds__(kFvRowThreads)
     k_fv_jacobi(int N, double ih2, double coef, const double* __restrict__ f,
-                const double* __restrict__ u, double* __restrict__ uout)
+                const double* __restrict__ u, double* __restrict__ uout, int zero)
 {
   const int x = 1 + blockIdx.x * kFvRowThreads + threadIdx.x, y = 1 + blockIdx.y, z = 1 + blockIdx.z;
   if (x > N) return;
   const size_t i = fidx(N + 2, z, y, x);
-  const double r = f[i] - fv_apply_at(N, ih2, u, z, y, x);
-  uout[i] = u[i] + coef * r;
+  const double r = f[i] - (zero ? 0.0 : fv_apply_at(N, ih2, u, z, y, x));
+  uout[i] = (zero ? 0.0 : u[i]) + coef * r;
 }
 
 // r on all (N+2)^3 entries: f - A u on the cells, 0 on the ghost layer
@@ -291,12 +292,12 @@ constexpr int kFvCoarseMax = (kFvCoarseLds + 2) * (kFvCoarseLds + 2) * (kFvCoars
 
 __global__ void __launch_bounds__(kFvCoarseThreads)
     k_fv_coarse(int N, double ih2, double coef, int iters, const double* __restrict__ f,
-                double* __restrict__ u)
+                double* __restrict__ u, int zero)
 {
   __shared__ double buf[2][kFvCoarseMax];
   const int m = N + 2;
   const int cnt = m * m * m, cells = N * N * N;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) buf[0][i] = buf[1][i] = u[i];
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) buf[0][i] = buf[1][i] = zero ? 0.0 : u[i];
   __syncthreads();
   int cur = 0;
   for (int it = 0; it < iters; ++it) {
@@ -322,18 +323,21 @@ __global__ void __launch_bounds__(kFvCoarseThreads)
 double jacobi_coef(const mgfv_ctx* c, const FvLevel& L) { return c->g.omega * (L.h * L.h / 6.0); }
 
 // `sweeps` Jacobi sweeps on level l from u (alternating with t, whose ghost layer equals
-// u's); returns the buffer that holds the result.
-double* smooth(mgfv_ctx* c, int l, double* u, double* t, const double* f, int sweeps)
+// u's); returns the buffer that holds the result.  zero: u is 0 (a coarse level's zero
+// correction, ghost layer 0) and is not read: the first sweep reads 0 instead.
+double* smooth(mgfv_ctx* c, int l, double* u, double* t, const double* f, int sweeps,
+               bool zero = false)
 {
   const FvLevel& L = c->lv[l];
   const double ih2 = 1.0 / (L.h * L.h);
   double *cur = u, *oth = t;
   for (int s = 0; s < sweeps; ++s) {
+    const bool z0 = zero && s == 0;
     if (mgk::fv_tiled_supported(L.N))
-      mgk::fv_jacobi_tiled(c->s, L.N, L.h, c->g.omega, f, cur, oth, c->partial);
+      mgk::fv_jacobi_tiled(c->s, L.N, L.h, c->g.omega, f, cur, oth, c->partial, z0);
     else
       k_fv_jacobi<<<grid3(L.N, L.N, L.N), kFvRowThreads, 0, c->s>>>(L.N, ih2, jacobi_coef(c, L),
-                                                                   f, cur, oth);
+                                                                   f, cur, oth, z0 ? 1 : 0);
     double* x = cur;
     cur = oth;
     oth = x;
@@ -341,15 +345,18 @@ double* smooth(mgfv_ctx* c, int l, double* u, double* t, const double* f, int sw
   return cur;
 }
 
-void coarse_solve(mgfv_ctx* c, int l, const double* f, double* u)
+// zero: u is 0 (not read)
+void coarse_solve(mgfv_ctx* c, int l, const double* f, double* u, bool zero = false)
 {
   const FvLevel& L = c->lv[l];
   const double ih2 = 1.0 / (L.h * L.h);
   if (L.N <= kFvCoarseLds) {
-    k_fv_coarse<<<1, kFvCoarseThreads, 0, c->s>>>(L.N, ih2, jacobi_coef(c, L), c->g.coarse_iters, f, u);
+    k_fv_coarse<<<1, kFvCoarseThreads, 0, c->s>>>(L.N, ih2, jacobi_coef(c, L), c->g.coarse_iters, f, u,
+                                                   zero ? 1 : 0);
     return;
   }
-  double* r = smooth(c, l, u, L.t, f, c->g.coarse_iters);
+  if (zero && c->g.coarse_iters == 0) mgk::fill<double>(c->s, L.cnt, 0.0, u);
+  double* r = smooth(c, l, u, L.t, f, c->g.coarse_iters, zero);
   if (r != u) mgk::copy<double>(c->s, L.cnt, r, u);
 }
 
@@ -384,18 +391,23 @@ void norm2(mgfv_ctx* c, const double* f, const double* u)
   k_fv_sum<<<1, 256, 0, c->s>>>(c->partial, kFvNormBlocks, c->scal);
 }
 
-// One V-cycle on level l from (u, t); returns the buffer holding the result.
-double* cycle(mgfv_ctx* c, int l, double* u, double* t, const double* f)
+// One V-cycle on level l from (u, t); returns the buffer holding the result.  zero: the
+// iterate is 0 (a coarse level's correction, with zero Dirichlet data) and is not read --
+// the first sweep starts from 0 instead of a filled array.
+double* cycle(mgfv_ctx* c, int l, double* u, double* t, const double* f, bool zero = false)
 {
   if (l == c->g.levels - 1) {
-    coarse_solve(c, l, f, u);
+    coarse_solve(c, l, f, u, zero);
     return u;
   }
-  double* cur = smooth(c, l, u, t, f, c->g.nu1);
+  if (zero && c->g.nu1 == 0) {
+    mgk::fill<double>(c->s, c->lv[l].cnt, 0.0, u);
+    zero = false;
+  }
+  double* cur = smooth(c, l, u, t, f, c->g.nu1, zero);
   FvLevel& C = c->lv[l + 1];
   restrict_residual(c, l, f, cur, C.f);
-  mgk::fill<double>(c->s, C.cnt, 0.0, C.u);  // zero correction, zero Dirichlet data
-  double* ec = cycle(c, l + 1, C.u, C.t, C.f);
+  double* ec = cycle(c, l + 1, C.u, C.t, C.f, true);  // zero correction, zero Dirichlet data
   double* oth = cur == u ? t : u;
   const FvLevel& F = c->lv[l];
   if (c->g.nu2 > 0 && mgk::fv_tiled_supported(F.N)) {

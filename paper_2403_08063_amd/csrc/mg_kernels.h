@@ -149,8 +149,9 @@ void zero_boundary(hipStream_t s, int dim, int n, double* p);
 // Exact-partition streaming passes for N >= 128 (mg_resid_tiled.hip):
 bool fv_tiled_supported(int N);
 // one damped Jacobi sweep, uout = u + omega h^2/6 (f - A u) on the cells (ghosts untouched)
+// zero_u: u is identically 0, ghost layer included (not read)
 void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double* f,
-                     const double* u, double* uout, double* partial);
+                     const double* u, double* uout, double* partial, bool zero_u = false);
 // the first post-smoothing sweep of a V-cycle: uout = Jacobi(u + P ec), with ec the coarse
 // correction ((N/2 + 2)^3 values, ghost layer not read) interpolated as the stand-alone
 // prolongation does; u itself is not modified

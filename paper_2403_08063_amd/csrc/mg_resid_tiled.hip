@@ -393,7 +393,7 @@ struct Pass {
     double inv_scale;    // refinement: r32 = r * inv_scale
     double coef;         // finite-volume Jacobi: u_out = u + coef * (f - A u)
     const double* ec;    // finite-volume prolongation: coarse correction, (N/2 + 2)^3
-    int zero_interior;   // norm: read the interior of u as 0
+    int zero_interior;   // norm: read the interior of u as 0; FV Jacobi: u is 0 (not read)
     int n;
     double ih2;
     int tiles_x, tiles_y, zlen;
@@ -563,13 +563,19 @@ struct Pass {
 #pragma unroll
     for (int p = 0; p < CP; ++p) PHE[p][0] = PHE[p][1] = 0.0f;
 
+    // finite-volume sweep from a zero iterate (a coarse level's first sweep: the correction
+    // and its ghost layer are 0): u is not read
+    const bool uzero = MODE == kFvJacobi && a.zero_interior;
     auto load_q = [&](int z) {
       const size_t zc = (size_t)min(max(z, 0), n - 1);
       const PlaneBuf bu = plane_buf(a.u, zc * planeb, planeb);
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
-        for (int p = 0; p < CP; ++p) buf_load2(bu, cb[p], rb8[i], PU[i][p][0], PU[i][p][1]);
+        for (int p = 0; p < CP; ++p) {
+          if (uzero) PU[i][p][0] = PU[i][p][1] = 0.0;
+          else buf_load2(bu, cb[p], rb8[i], PU[i][p][0], PU[i][p][1]);
+        }
       if constexpr (VAR) {
         const PlaneBuf bk = plane_buf(a.k, zc * planeb, planeb);
 #pragma unroll
@@ -662,14 +668,15 @@ struct Pass {
       for (int i = 0; i < RPW; ++i) {
 #pragma unroll
         for (int p = 0; p < CP; ++p) buf_load2(bf, cb[p], rb8[i], PF[i][p][0], PF[i][p][1]);
-        PX[i] = buf_load<double>(bu, hcb, rb8[i]);
+        PX[i] = uzero ? 0.0 : buf_load<double>(bu, hcb, rb8[i]);
         if constexpr (VAR) PXK[i] = buf_load<double>(bk, hcb, rb8[i]);
         if (corr) PXE[i] = buf_load<float>(be, hcf, rb4[i]);
       }
       if (hw) {
 #pragma unroll
         for (int p = 0; p < CP; ++p) {
-          buf_load2(bu, cb[p], hrb8, PH[p][0], PH[p][1]);
+          if (uzero) PH[p][0] = PH[p][1] = 0.0;
+          else buf_load2(bu, cb[p], hrb8, PH[p][0], PH[p][1]);
           if constexpr (VAR) buf_load2(bk, cb[p], hrb8, PHK[p][0], PHK[p][1]);
           if (corr) buf_load2(be, cf[p], hrb4, PHE[p][0], PHE[p][1]);
         }
@@ -1196,10 +1203,11 @@ void launch_fv(hipStream_t s, int N, double* partial, double* out, Fill fill)
 bool fv_tiled_supported(int N) { return N >= 128; }
 
 void fv_jacobi_tiled(hipStream_t s, int N, double h, double omega, const double* f,
-                     const double* u, double* uout, double* partial)
+                     const double* u, double* uout, double* partial, bool zero_u)
 {
   launch_fv<kFvJacobi>(s, N, partial, nullptr, [&](auto& a) {
     a.f = f; a.u = u; a.out = uout; a.ih2 = 1.0 / (h * h); a.coef = omega * (h * h / 6.0);
+    a.zero_interior = zero_u ? 1 : 0;
   });
 }
 
