@@ -49,6 +49,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -288,7 +289,8 @@ def _short_kernel_name(name: str) -> str:
 def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24, by_grid: bool = False):
     """Markdown summary of a `rocprofv3 --kernel-trace --stats` run of this script: the
     per-kernel table and the mean duration of the fine-level FP64 smoother launches (the
-    largest grid of k_rbgs_tiled<double, ...>), beside bench.py's own HIP-event figure;
+    largest grid of the plain k_rbgs_tiled<double, ...> pass), beside bench.py's own
+    HIP-event figure;
     by_grid adds a table per kernel and launch grid (the levels of a multigrid run)."""
     import csv
     import glob
@@ -305,10 +307,14 @@ def summarize_trace(trace_dir: str, bench_log: str = None, top: int = 24, by_gri
         lines.append(f"| `{_short_kernel_name(r['Name'])}` | {r['Calls']} | {t / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {100 * t / total:.1f}% |")
     launches = []
+    # the plain smoother (2 sweeps, input read, no fused transfer: template arguments
+    # <double, false, 2, waves, rows, prefetch, 0, 0, lanes>), the kernel bench.py times
+    plain = re.compile(r"<double, false, 2, \d+, \d+, \d+, 0, 0, \d+>$")
     for r in csv.DictReader(open(trace[0])):
-        if SMOOTHER_KERNEL + "<double" in r["Kernel_Name"]:
+        short = _short_kernel_name(r["Kernel_Name"])
+        if short.startswith(SMOOTHER_KERNEL + "<double") and plain.search(short):
             grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-            launches.append((grid, _short_kernel_name(r["Kernel_Name"]),
+            launches.append((grid, short,
                              (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
     head = []
     if launches:
