@@ -446,7 +446,13 @@ struct Tiled {
             yp = sh.eu[rb][pslot][wp][0][lane];
             if constexpr (VAR) kyp = sh.ek[rb][pslot][wp][0][lane];
           }
-          const T zm = U[cm][i][o], zp = U[cp][i][o];
+          T zm = U[cm][i][o], zp = U[cp][i][o];
+          if (IN == kInZero && j == 0) {
+            // from a zero guess the first stage's neighbours are all still 0 (the other
+            // colour of planes p-1, p, p+1 and the boundary): the same formula on literal
+            // zeros, which the compiler folds
+            xm = xp = ym = yp = zm = zp = T(0);
+          }
           const T h2f = h2 * F[cs][i][o];
           T v;
           if (!VAR) {
