@@ -211,8 +211,12 @@ T* smooth(mg_ctx* c, int l, T* u, T* t, const T* f, const T* k, int sweeps, bool
   const Level& L = c->lv[l];
   const int dim = c->g.dim;
   const bool tiled = use_tiled(c, l);
+  // the blocked pass that takes the correction is the first one: two sweeps unless only one
+  // is asked for (FP64 passes fuse the correction into 2-sweep passes only)
+  const bool pair = sweeps >= 2 && mgk::rbgs_tiled_max_sweeps(k != nullptr, sizeof(T)) == 2;
   if (ec && (sweeps == 0 || !(c->fuse & MG_FUSE_PROLONG) ||
-             (tiled && !mgk::rbgs_tiled_fuses_prolong(sizeof(T), k != nullptr)))) {
+             (tiled && (!mgk::rbgs_tiled_fuses_prolong(sizeof(T), k != nullptr) ||
+                        (sizeof(T) == 8 && !pair))))) {
     // coarse-grid correction as a separate pass when it cannot ride on a fused sweep
     mgk::prolong_add<T>(c->s, dim, c->lv[l + 1].n, ec, u);
     ec = nullptr;

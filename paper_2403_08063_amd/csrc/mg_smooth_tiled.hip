@@ -648,6 +648,18 @@ LaunchShape shape_for(int n, int capacity)
 // of 2 rows (64 x 32-node tiles) fit in 200-208 VGPRs; 10 x 2 and 8 x 4 spill, 12 x 2
 // exceeds the LDS.  FP64 solve at 513^3: 27.3 ms against 29.0 with the separate
 // restriction pass.
+// The FP64 variable-coefficient pass holds k beside u and f: with 2 sweeps per pass, 8
+// waves of 2 rows (both layouts) fit in 192-214 VGPRs; 8 x 4 spills.  Workload 4's FP64
+// solve at 257^3: 16.5 ms, against 21.7 ms with one sweep per pass.
+#ifndef MG_SMOOTH64_VAR_W
+#define MG_SMOOTH64_VAR_W 8
+#endif
+#ifndef MG_SMOOTH64_VAR_RPW
+#define MG_SMOOTH64_VAR_RPW 2
+#endif
+#ifndef MG_SMOOTH64_VAR_NARROW
+#define MG_SMOOTH64_VAR_NARROW 1
+#endif
 #ifndef MG_SMOOTH64_RES_W
 #define MG_SMOOTH64_RES_W 8
 #endif
@@ -664,12 +676,14 @@ template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
   static constexpr int W = RES                ? (f32 ? MG_SMOOTH32_RES_W : MG_SMOOTH64_RES_W)
+                           : (!f32 && VAR && S == 2) ? MG_SMOOTH64_VAR_W
                            : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_W
                            : !(f32 && plain)   ? MG_SMOOTH_W
                            : IN == kInProlong ? MG_SMOOTH32_PROLONG_W
                            : IN == kInZero    ? MG_SMOOTH32_ZERO_W
                                               : MG_SMOOTH32_READ_W;
   static constexpr int RPW = RES                ? (f32 ? MG_SMOOTH32_RES_RPW : MG_SMOOTH64_RES_RPW)
+                             : (!f32 && VAR && S == 2) ? MG_SMOOTH64_VAR_RPW
                              : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_RPW
                              : !(f32 && plain)   ? MG_SMOOTH_RPW
                              : IN == kInProlong ? MG_SMOOTH32_PROLONG_RPW
@@ -686,6 +700,7 @@ struct Shape {
   // second prefetch buffer or 6 rows per wave in the restriction)
   static constexpr bool NARROW = RES ? MG_SMOOTH32_RES_NARROW
                                  : IN == kInProlong ? MG_SMOOTH32_PROLONG_NARROW
+                                 : (!f32 && VAR && S == 2) ? MG_SMOOTH64_VAR_NARROW
                                                     : !(VAR && !f32);
 };
 
@@ -722,9 +737,14 @@ void launch_cfg(hipStream_t s, int n, double h, const T* k, const T* f, const T*
                 bool zero_in, const T* ec)
 {
   if (ec) {
-    // FP32 passes and the plain FP64 pass fuse the prolongation (rbgs_tiled_fuses_prolong)
-    if constexpr (sizeof(T) == 4 || (!VAR && S == 2))
+    // FP32 passes and 2-sweep FP64 passes fuse the prolongation (rbgs_tiled_fuses_prolong);
+    // a one-sweep FP64 pass, which the host does not ask for, adds it first
+    if constexpr (sizeof(T) == 4 || S == 2) {
       launch_in<T, VAR, S, kInProlong>(s, n, h, k, f, uin, uout, ec);
+    } else {
+      prolong_add<T>(s, 3, (n - 1) / 2 + 1, ec, const_cast<T*>(uin));
+      launch_in<T, VAR, S, kInRead>(s, n, h, k, f, uin, uout, ec);
+    }
   } else if (zero_in) launch_in<T, VAR, S, kInZero>(s, n, h, k, f, uin, uout, ec);
   else launch_in<T, VAR, S, kInRead>(s, n, h, k, f, uin, uout, ec);
 }
@@ -741,16 +761,19 @@ bool rbgs_tiled_supported(int dim, int n) { return dim == 3 && n > MG_TILED_MIN_
 
 bool rbgs_tiled_fuses_prolong(size_t value_bytes, bool var)
 {
-  // the FP64 variable-coefficient pass (one sweep, k in registers) has no registers left
-  // for the coarse-grid correction
-  return value_bytes == 4 || !var;
+  // every 2-sweep pass takes the coarse-grid correction (the FP64 variable-coefficient one
+  // on its 8 x 2-row tiles: 220-234 VGPRs)
+  (void)value_bytes;
+  (void)var;
+  return true;
 }
 
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes)
 {
-  // the FP64 variable-coefficient pass keeps k in registers too: one sweep per pass keeps
-  // it free of register spills
-  return (var && value_bytes == 8) ? 1 : 2;
+  // every pass fuses two sweeps (the FP64 variable-coefficient pass on 8 x 2-row tiles)
+  (void)var;
+  (void)value_bytes;
+  return 2;
 }
 
 bool rbgs_tiled_fuses_restrict(size_t value_bytes, bool var)
@@ -771,10 +794,9 @@ void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T*
       return;
     }
   }
-  // the host asks for 2 sweeps with k only in FP32 (rbgs_tiled_max_sweeps)
   if (sweeps == 2) {
     if (k) {
-      if constexpr (sizeof(T) == 4) launch_cfg<T, true, 2>(s, n, h, k, f, uin, uout, zero_in, ec);
+      launch_cfg<T, true, 2>(s, n, h, k, f, uin, uout, zero_in, ec);
     } else {
       launch_cfg<T, false, 2>(s, n, h, k, f, uin, uout, zero_in, ec);
     }

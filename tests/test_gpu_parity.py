@@ -248,6 +248,35 @@ def test_vcycle_matches_oracle(oracle, dim, n, levels, var):
     assert relmax(host(ug), uo) <= 1e-12
 
 
+@pytest.mark.parametrize("nu1,nu2,var,prec", [(1, 1, False, "f64"), (3, 3, False, "f64"),
+                                               (1, 3, True, "f64"), (3, 1, False, "f32_ir")])
+def test_vcycle_odd_sweep_counts(oracle, nu1, nu2, var, prec):
+    """V(nu1, nu2) with odd sweep counts on blocked levels: a one-sweep pass ends the
+    smoothing, and the coarse-grid correction rides on a 2-sweep pass or is added by a
+    pass of its own (nu2 = 1), against the oracle's V-cycle."""
+    n, levels = 161, 6
+    say(f"vcycle nu=({nu1},{nu2}) var={var} prec={prec}")
+    k = random_k(3, n, 27) if var else None
+    f = inputs.uniform_interior(3, n, 28)
+    u0 = random_interior(3, n, 29, 0.1)
+    mg = Multigrid(3, n, levels, nu1=nu1, nu2=nu2, variable=var, device=DEV)
+    if var:
+        mg.set_coefficients(dev(k))
+    ug = dev(u0)
+    for _ in range(2):
+        mg.vcycle(dev(f), ug)
+    uo = u0.copy()
+    for _ in range(2):
+        oracle.vcycle(f, uo, levels, k=k, nu1=nu1, nu2=nu2)
+    assert relmax(host(ug), uo) <= 1e-12
+    if prec == "f32_ir":
+        mgi = Multigrid(3, n, levels, nu1=nu1, nu2=nu2, precision="f32_ir", device=DEV)
+        u, info = mgi.solve(dev(f), tol=1e-10)
+        assert info.relres <= 1e-10 and oracle.rel_residual(f, host(u), None) <= 1.5e-10
+        mgi.close()
+    mg.close()
+
+
 SOLVE_CASES = [  # name, dim, n, levels, f builder, k builder
     ("workload1-2D-129", 2, 129, 6, lambda: inputs.manufactured_f(2, 129), None),
     ("3D-65", 3, 65, 6, lambda: inputs.uniform_interior(3, 65, 3), None),
