@@ -165,17 +165,25 @@ mg_status mg_residual_norm2(mg_ctx* ctx, const double* f, const double* u, doubl
  *  MG_FUSE_TAIL     all levels with at most 4096 interior nodes in one launch;
  *  MG_FUSE_RESTRICT on such large 3D levels, the residual and its full-weighting restriction
  *                   computed inside the pre-smoothing pass (constant coefficient, FP32
- *                   and FP64) instead of a separate pass.
+ *                   and FP64) instead of a separate pass;
+ *  MG_FUSE_REFINE   in an MG_F32_IR solve with a large 3D finest level, a constant
+ *                   coefficient and nu2 = 2 (with MG_FUSE_PROLONG), the refinement step
+ *                   (u += s e, the FP64 residual, its norm and the next FP32 right-hand side)
+ *                   performed inside the FP32 cycle's last post-smoothing pass instead of a
+ *                   separate pass, so the correction is never stored.
  * Default MG_FUSE_ALL.  Clearing MG_FUSE_PROLONG, MG_FUSE_ZERO, MG_FUSE_TAIL or
  * MG_FUSE_RESTRICT leaves every result bitwise unchanged; without MG_FUSE_BLOCKED smoothing results are unchanged but
- * residual sums are accumulated in another order.  EINVAL for bits outside MG_FUSE_ALL. */
+ * residual sums are accumulated in another order; MG_FUSE_REFINE leaves the iterate bitwise
+ * unchanged and sums the residual norm in another order.  EINVAL for bits outside
+ * MG_FUSE_ALL. */
 enum {
   MG_FUSE_BLOCKED = 1,
   MG_FUSE_PROLONG = 2,
   MG_FUSE_ZERO = 4,
   MG_FUSE_TAIL = 8,
   MG_FUSE_RESTRICT = 16,
-  MG_FUSE_ALL = 31
+  MG_FUSE_REFINE = 32,
+  MG_FUSE_ALL = 63
 };
 mg_status mg_set_fusion(mg_ctx* ctx, int flags);
 

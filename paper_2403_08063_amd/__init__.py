@@ -17,9 +17,9 @@ from .autograd import MGSolve, solve  # noqa: F401
 from .fv import FVMultigrid  # noqa: F401
 from .blocks import RefinedBlocks  # noqa: F401
 from .galerkin import GalerkinMultigrid  # noqa: F401
-from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_RESTRICT, FUSE_TAIL,  # noqa: F401
-                   FUSE_ZERO, MgError)
+from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_REFINE, FUSE_RESTRICT,  # noqa: F401
+                   FUSE_TAIL, FUSE_ZERO, MgError)
 
 __all__ = ["Multigrid", "FVMultigrid", "RefinedBlocks", "GalerkinMultigrid", "SolveInfo", "MGSolve", "solve", "MgError", "default_levels",
-           "FUSE_ALL", "FUSE_BLOCKED", "FUSE_PROLONG", "FUSE_RESTRICT", "FUSE_TAIL",
+           "FUSE_ALL", "FUSE_BLOCKED", "FUSE_PROLONG", "FUSE_REFINE", "FUSE_RESTRICT", "FUSE_TAIL",
            "FUSE_ZERO"]

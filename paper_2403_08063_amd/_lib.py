@@ -18,7 +18,8 @@ MG_F64, MG_F32_IR = 0, 1
 NOALLOC_MAX_BYTES = 32 << 20  # MG_NOALLOC_MAX_BYTES of include/mg.h
 # kernel-fusion flags (mg_set_fusion)
 FUSE_BLOCKED, FUSE_PROLONG, FUSE_ZERO, FUSE_TAIL, FUSE_RESTRICT = 1, 2, 4, 8, 16
-FUSE_ALL = 31
+FUSE_REFINE = 32
+FUSE_ALL = 63
 
 # every function declared in include/mg.h
 EXPORTS = [

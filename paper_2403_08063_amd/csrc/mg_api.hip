@@ -47,7 +47,7 @@ struct mg_ctx {
   int* flag = nullptr;
   double* partial = nullptr;
   double* partial_b = nullptr;  // second partial sums (right-hand-side norm of the first pass)
-  double* scal = nullptr;  // device scalars: [0] norm2, [1] rhs norm2
+  double* scal = nullptr;  // device scalars: [0] norm2, [1] rhs norm2, [4..5] fused-solve scales
   double last_bn = 0.0;    // right-hand-side norm of the previous solve (0: none)
   bool coeffs = false;
   int fuse = MG_FUSE_ALL;  // kernel-fusion flags (mg_set_fusion)
@@ -390,6 +390,52 @@ mg_status read_scalar_finish(mg_ctx* c, double* host, int count = 1)
   return MG_OK;
 }
 
+// Whether the FP32 correction cycle's last level-0 post-smoothing pass can also perform the
+// refinement step (rbgs_tiled_refine): a blocked level 0 with a constant coefficient, one
+// 2-sweep post-smoothing pass that takes the coarse-grid correction.
+bool refine_fusable(const mg_ctx* c)
+{
+  return (c->fuse & MG_FUSE_REFINE) && (c->fuse & MG_FUSE_PROLONG) && use_tiled(c, 0) &&
+         !c->g.variable && c->g.nu2 == 2 && mgk::rbgs_tiled_max_sweeps(false, 4) == 2;
+}
+
+// Level-0 FP32 buffers of a fused solve: the cycle's right-hand side and the two buffers of
+// its correction.  The fused pass writes the next right-hand side into the buffer that
+// holds neither the correction nor the current right-hand side, so the three rotate.  k
+// counts the cycles: the right-hand side's scale is the device scalar ss[k mod 2], the next
+// one's ss[(k+1) mod 2].
+struct FusedIr {
+  float *rhs, *u, *t;
+  int k;
+};
+
+// One FP32 correction cycle from e = 0 on the right-hand side st.rhs, with its last pass
+// fused with the refinement step: uout = u + s e, the next right-hand side, the residual
+// norm into scal[0] and the scale after the next one into ss[k mod 2] (read by the cycle
+// after next, stream-ordered).
+mg_status fused_ir_cycle(mg_ctx* c, const double* f, const double* u, double* uout, FusedIr& st)
+{
+  const Level& L0 = c->lv[0];
+  const View<float> C = view<float>(c, 1);
+  const bool fuse_r = (c->fuse & MG_FUSE_RESTRICT) && c->g.nu1 == 2 &&
+                      mgk::rbgs_tiled_fuses_restrict(sizeof(float), false);
+  float* cur = smooth<float>(c, 0, st.u, st.t, st.rhs, nullptr, c->g.nu1, true, nullptr,
+                             fuse_r ? C.f : nullptr);
+  if (!fuse_r) mgk::restrict_residual_tiled<float>(c->s, L0.n, L0.h, nullptr, st.rhs, cur, C.f);
+  float* ec = cycle<float>(c, 1, C.u, C.t, C.f, true);
+  float* next = cur == st.u ? st.t : st.u;
+  double* ss = c->scal + 4;
+  if (!mgk::rbgs_tiled_refine(c->s, L0.n, L0.h, st.rhs, cur, ec, f, u, uout, next,
+                              ss + (st.k & 1), ss + ((st.k + 1) & 1), c->partial, c->scal,
+                              ss + (st.k & 1)))
+    return fail(c, MG_EINVAL, "grid too large for the fused refinement pass");
+  st.u = st.rhs;
+  st.t = cur;
+  st.rhs = next;
+  ++st.k;
+  return launch_check(c, "V-cycle with the refinement step");
+}
+
 // Refinement on a large 3D grid with the fused pass (mg_resid_tiled.hip): every pass
 // applies the previous FP32 correction, forms the FP64 residual, its norm and the scaled
 // FP32 right-hand side of the next cycle, writing the updated iterate out of place (u and
@@ -415,12 +461,21 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
   double* cur = u;
   double* other = L0.t;
   const bool fused_rhs = !(bn > 0);
+  // The correction cycle's last pass may also apply the correction and form the next
+  // residual (refine_fusable): the speculative cycle below then writes the iterate (out of
+  // place) and the scales of the right-hand sides live on the device.  A first pass that
+  // may have to be repeated with another scale (fused_rhs) is then not overlapped, since
+  // its repetition reads the buffer that such a cycle writes.
+  const bool fused = refine_fusable(c);
+  FusedIr fst{L0.f32, L0.u32, L0.t32, 0};
+  bool no_spec = fused && fused_rhs;
   double scale = ir_scale(c, fused_rhs ? c->last_bn : bn);  // scale of the r32 being written
   double rn2 = 0;
   const bool overlap = c->hnorm != nullptr && c->ev != nullptr;
   mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other, L0.f32,
                      c->partial, c->scal, fused_rhs ? c->partial_b : nullptr);
   std::swap(cur, other);
+  if (fused) mgk::ir_scales_init(c->s, L0.n, c->scal, scale, c->scal + 4);
   mg_status st = launch_check(c, "refinement pass");
   // relative residual predicted for the norm in flight (infinite: no history yet)
   double predicted = INFINITY, rel_prev = NAN;
@@ -434,10 +489,16 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
       return s2;
     }
     mg_status s2 = read_scalar_start(c, c->scal, count);
-    if (!s2 && predicted > 4.0 * tol && c->g.max_cycles > 0) {
-      spec = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
-      s2 = launch_check(c, "V-cycle");
+    if (!s2 && !no_spec && predicted > 4.0 * tol && c->g.max_cycles > 0) {
+      if (fused) {
+        s2 = fused_ir_cycle(c, f, cur, other, fst);
+        spec = fst.rhs;  // marks the cycle as enqueued
+      } else {
+        spec = cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+        s2 = launch_check(c, "V-cycle");
+      }
     }
+    no_spec = false;
     if (!s2) s2 = read_scalar_finish(c, out, count);
     return s2;
   };
@@ -457,6 +518,7 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
       mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other,
                          L0.f32, c->partial, c->scal);
       std::swap(cur, other);
+      if (fused) mgk::ir_scales_init(c->s, L0.n, c->scal, scale, c->scal + 4);
       st = launch_check(c, "refinement pass");
       if (!st) st = read_norm(&rn2, 1);
     }
@@ -467,15 +529,23 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
   double rel = std::sqrt(rn2) / bn;
   int k = 0;
   while (!st && std::isfinite(rel) && rel > tol && k < c->g.max_cycles) {
-    float* e = spec ? spec : cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
-    spec = nullptr;
-    const double next = ir_scale(c, std::sqrt(rn2));
-    mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, e, scale, 1.0 / next, other, L0.f32,
-                       c->partial, c->scal);
-    std::swap(cur, other);
-    scale = next;
-    ++k;
-    if ((st = launch_check(c, "refinement pass"))) break;
+    if (fused) {
+      if (!spec) st = fused_ir_cycle(c, f, cur, other, fst);
+      spec = nullptr;
+      std::swap(cur, other);
+      ++k;
+      if (st) break;
+    } else {
+      float* e = spec ? spec : cycle<float>(c, 0, L0.u32, L0.t32, L0.f32, true);
+      spec = nullptr;
+      const double next = ir_scale(c, std::sqrt(rn2));
+      mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, e, scale, 1.0 / next, other, L0.f32,
+                         c->partial, c->scal);
+      std::swap(cur, other);
+      scale = next;
+      ++k;
+      if ((st = launch_check(c, "refinement pass"))) break;
+    }
     // contraction so far: the next relative residual is about rel * (rel / rel_prev)
     const double rho = std::isfinite(rel_prev) && rel_prev > 0 ? rel / rel_prev : 1.0;
     predicted = k < c->g.max_cycles ? rel * rho : 0.0;

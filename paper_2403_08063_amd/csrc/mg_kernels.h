@@ -44,6 +44,24 @@ bool rbgs_tiled_supported(int dim, int n);
 int rbgs_tiled_max_sweeps(bool var, size_t value_bytes);
 bool rbgs_tiled_fuses_prolong(size_t value_bytes, bool var);
 bool rbgs_tiled_fuses_restrict(size_t value_bytes, bool var);
+// The last FP32 post-smoothing of a correction cycle (constant coefficient, two sweeps, the
+// coarse-grid correction ec taken in, right-hand side rhs, input ein) fused with the
+// refinement step that follows it: with e the smoothed correction (not stored),
+// uout = u + s_e e on interior nodes (boundary of uout not written), r = f - A uout,
+// r32 = (float)(r / s_r), norm2[0] = sum of r^2 over interior nodes, scale_next[0] = the
+// scale of the next right-hand side (the power of two nearest in log2 to the residual's
+// root mean square).  s_e = scale_e[0], s_r = scale_r[0] are device scalars, read by the
+// kernel.  The arithmetic of uout and r32 is that of rbgs_tiled followed by ir_pass_tiled;
+// the sum runs in another order.  partial: kStreamPartials doubles.  r32 and rhs, uout and
+// u must not overlap.  Returns false, launching nothing, if the grid needs more than
+// kStreamPartials workgroups.
+bool rbgs_tiled_refine(hipStream_t s, int n, double h, const float* rhs, const float* ein,
+                       const float* ec, const double* f, const double* u, double* uout,
+                       float* r32, const double* scale_e, const double* scale_r,
+                       double* partial, double* norm2, double* scale_next);
+// ss[0] = scale0, ss[1] = the scale (as rbgs_tiled_refine's scale_next) of the residual whose
+// squares sum to norm2[0]: the scales of the first two right-hand sides of a fused solve.
+void ir_scales_init(hipStream_t s, int n, const double* norm2, double scale0, double* ss);
 
 // r = f - A u (interior), 0 on the boundary.
 template <typename T>

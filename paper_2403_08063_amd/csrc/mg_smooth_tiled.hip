@@ -49,6 +49,18 @@ enum { kInRead = 0, kInZero = 1, kInProlong = 2 };
 
 constexpr int imod(int a, int m) { return ((a % m) + m) % m; }
 
+// Operands of the fused refinement (RES = 2); unused by the other passes.
+struct RefineArgs {
+  const double* u;        // FP64 iterate
+  double* out;            // u + s_e e on interior nodes (boundary not written)
+  const double* f;        // FP64 right-hand side
+  float* r32;             // (f - A out) / s_r on interior nodes
+  const double* scale_e;  // device scalar s_e (the scale of the cycle's right-hand side)
+  const double* scale_r;  // device scalar s_r
+  double ih2;             // 1 / h^2
+  double* partial;        // per-workgroup sums of (f - A out)^2 over interior nodes
+};
+
 // RES = 1: the pass also computes the residual f - A u of the smoothed iterate and its
 // full-weighting restriction onto the next coarser level (the smoother's output stays in
 // registers instead of being read back by a separate restriction pass).  The residual of
@@ -56,6 +68,16 @@ constexpr int imod(int a, int m) { return ((a % m) + m) % m; }
 // final: two more queued planes, a 4-node wider tile overlap in x and y (the residual is
 // exact one node, its full weighting two nodes further inside than the final values) and
 // 2 more final planes at each end of the z-chunk.
+//
+// RES = 2 (FP32, constant coefficient, 2 sweeps, with the coarse-grid correction): the pass
+// is the last post-smoothing of an FP32 correction cycle and also performs the iterative
+// refinement step that follows it -- u_out = u + s_e e on interior nodes (u, u_out FP64),
+// r = f - A u_out in FP64, r32 = (float)(r / s_r) and the sum of r^2 -- with the arithmetic of
+// the separate refinement pass, so the smoothed correction is never stored.  The residual of
+// plane q needs the corrected iterate on planes q-1, q, q+1, formed as each plane of the
+// correction becomes final: a 2-node wider tile overlap in x and y (the residual is exact
+// one node further inside than the correction) and one more final plane at each end of the
+// z-chunk; the corrected planes wait in a ring of three per lane.
 //
 // LW = lanes per tile row: 64 (a wave's lanes span the tile's 128 columns), or 32 (the tile
 // is 64 columns wide and each wave holds two row bands of RPW rows, lanes 0-31 the first and
@@ -69,32 +91,37 @@ template <typename T, bool VAR, int S, int W, int RPW, int PD, int RES = 0, int 
 struct Tiled {
   static_assert(PD == 1 || PD == 2, "prefetch depth");
   static_assert(RES == 0 || (!VAR && S == 2), "the fused restriction serves the plain 2-sweep pass");
+  static_assert(RES != 2 || sizeof(T) == 4, "the fused refinement follows an FP32 cycle");
+  static constexpr bool REF = RES == 2;
   static_assert(LW == 64 || LW == 32, "lanes per tile row");
   static constexpr int G = 64 / LW;      // row groups per wave
   static constexpr int VW = W * G;       // row groups per tile
   static constexpr int H = 2 * S;        // halo = number of stages
   static constexpr int BX = 2 * LW;      // columns per tile (2 per lane)
   static constexpr int BY = VW * RPW;    // rows per tile
-  static constexpr int XR = RES ? 4 : 0; // extra overlap for the fused restriction
-  static constexpr int ZR = RES ? 2 : 0; // extra final planes at each end of a z-chunk
+  static constexpr int XR = RES == 1 ? 4 : REF ? 2 : 0;  // extra overlap: restriction, refinement
+  static constexpr int ZR = RES == 1 ? 2 : REF ? 1 : 0;  // extra final planes at each end of a z-chunk
   static constexpr int TXO = BX - 2 * H - XR; // output columns per tile (tile stride)
   static constexpr int TYO = BY - 2 * H - XR; // output rows per tile
-  static constexpr int Q = H + 2 + (RES ? 2 : 0);  // planes held per lane (even)
+  static constexpr int Q = H + 2 + (RES == 1 ? 2 : 0);  // planes held per lane (even)
+  static_assert(!REF || Q % 3 == 0, "the ring of corrected planes follows the queue's phases");
   static_assert(RPW % 2 == 0, "row parity must be uniform across the waves of a tile");
   static_assert(TYO > 0, "tile too short for the halo");
 
   struct Shared {
     T eu[2][H][VW][2][LW];                     // row-group boundary rows of u
     T ek[VAR ? 2 : 1][VAR ? H : 1][VW][2][LW]; // and of k
-    T er[RES ? 2 : 1][RES ? VW : 1][2][2][LW]; // RES: both columns of a final plane's edge rows
-    T erx[RES ? 2 : 1][RES ? VW : 1][LW];      // RES: x-filtered residual of a group's first row
+    T er[RES == 1 ? 2 : 1][RES == 1 ? VW : 1][2][2][LW]; // RES 1: both columns of a final plane's edge rows
+    T erx[RES == 1 ? 2 : 1][RES == 1 ? VW : 1][LW];      // RES 1: x-filtered residual of a group's first row
+    double eun[REF ? 2 : 1][REF ? VW : 1][2][2][LW];     // REF: edge rows of a corrected plane
+    double red[REF ? W : 1];                             // REF: per-wave sums of r^2
   };
 
   // The first column of every lane and the first row of every row group have odd global
   // indices (tile origins are odd, H and RPW even): the fused prolongation relies on it.
   static_assert(TXO % 2 == 0 && TYO % 2 == 0 && H % 2 == 0, "odd tile origins");
 
-  // B0 = parity of (global x of column 0) + (global y of row 0) + z0 - 1 (see below).
+  // B0 = parity of (global x of column 0) + (global y of row 0) + z0 - 1 + ZR (see below).
   // IN: how the input is formed -- kInRead: uin; kInZero: 0 (uin not read);
   // kInProlong: uin + P ec, the coarse-grid correction ec (nc nodes per side) interpolated
   // with the same weights and summation order as the stand-alone prolongation kernel.
@@ -103,8 +130,10 @@ struct Tiled {
                                              const T* __restrict__ f, const T* __restrict__ k,
                                              const T* __restrict__ ec, int nc,
                                              int n, T h2, int ox, int oy, int z0, int z1,
-                                             T ih2, T* __restrict__ fc, Shared& sh)
+                                             T ih2, T* __restrict__ fc, const RefineArgs& ra,
+                                             Shared& sh)
   {
+    static_assert(!REF || IN == kInProlong, "the fused refinement follows the post-smoothing");
     // lane within its row group, and the row group (wave-uniform for LW = 64, so that row
     // bookkeeping stays scalar there)
     const int lane = threadIdx.x & (LW - 1);
@@ -265,7 +294,7 @@ struct Tiled {
     // final plane pout (queue slot SO) -> uout, if it belongs to this z-chunk
     auto store = [&](int pout, auto SOC) {
       constexpr int so = decltype(SOC)::value;
-      if (pout < z0 || pout >= z1) return;
+      if (REF || pout < z0 || pout >= z1) return;  // REF: the correction is not stored
       const PlaneBuf bo = plane_buf(uout, (size_t)pout * planeb, planeb);
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
@@ -286,7 +315,7 @@ struct Tiled {
 
     const int zbeg = z0 - H - ZR, zend = z1 + H + ZR;  // planes loaded: [zbeg, zend)
     // RES: one more step completes the restriction of the last residual plane
-    const int zstop = zend + (RES ? 1 : 0);
+    const int zstop = zend + (RES == 1 ? 1 : 0);
     int zl = zbeg;
 
     // Fused restriction (RES): lane column 1 is the even fine column 2X of coarse column X
@@ -296,7 +325,7 @@ struct Tiled {
     // nodes inside the loaded tile, or next to the grid boundary, whose values are exact.
     const int gxc = gxa + 1;
     const int xlo = ox == 1 ? 2 : ox + 2, ylo = oy == 1 ? 2 : oy + 2;
-    const bool cown = RES && gxc >= xlo && gxc < ox + 2 + TXO && gxc <= n - 3;
+    const bool cown = RES == 1 && gxc >= xlo && gxc < ox + 2 + TXO && gxc <= n - 3;
     unsigned crown = 0;
 #pragma unroll
     for (int i = 1; i < RPW; i += 2) {
@@ -314,8 +343,8 @@ struct Tiled {
     // One step for phase P = step mod Q: the plane zl - d sits in queue slot (P - d) mod Q.
     // The update column of row i in this step is o_i = (B0 + i + P) & 1, because the
     // colour of (x, y, p) is (x + y + p) & 1 and, at stage j, colour j&1 and p = zl-1-j
-    // make x's parity depend on zl only.  Tile origins are odd, so B0 = (z0 - 1) & 1, and
-    // zl = z0 - H - ZR + step with H, ZR and Q even: zl has the parity (B0 + 1 + P) & 1,
+    // make x's parity depend on zl only.  Tile origins are odd, so B0 = (z0 - 1 + ZR) & 1,
+    // and zl = z0 - H - ZR + step with H and Q even: zl has the parity (B0 + 1 + P) & 1,
     // and the step that of P.
     // RES, at the end of step zl (phase P): (1) full weighting in y and z of the residual
     // plane zl-H-2, x-filtered in the previous step; (2) residual of plane q = zl-H-1 (its
@@ -384,6 +413,135 @@ struct Tiled {
       }
     };
 
+    // Fused refinement (REF).  Nodes whose residual this tile owns: columns [rxlo, rxhi) and
+    // rows [rylo, ryhi) (from 1 in the first tile; tiles advance by TXO, TYO), planes
+    // [z0, z1); each lies at least H + 1 nodes inside the loaded tile, or next to the grid
+    // boundary.  The FP64 iterate is loaded on the owned nodes and one node around them,
+    // f on the owned nodes; other lanes' accesses take an out-of-range offset (no traffic).
+    constexpr uint32_t kOff = 0x80000000u;
+    unsigned rown = 0, rneed = 0;  // bit 2i+o: owned node; node whose iterate is loaded
+    uint32_t dxo[2] = {kOff, kOff}, dxn[2] = {kOff, kOff};  // FP64 column byte offsets
+    if constexpr (REF) {
+      const int rxlo = ox == 1 ? 1 : ox + 1, rxhi = min(ox + 1 + TXO, n - 1);
+      const int rylo = oy == 1 ? 1 : oy + 1, ryhi = min(oy + 1 + TYO, n - 1);
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int gx = gxa + o;
+        const bool xo = gx >= rxlo && gx < rxhi, xn = gx >= rxlo - 1 && gx <= rxhi;
+        dxo[o] = xo ? (uint32_t)gx * 8u : kOff;
+        dxn[o] = xn ? (uint32_t)gx * 8u : kOff;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int gy = gyw + i;
+          const bool yo = gy >= rylo && gy < ryhi, yn = gy >= rylo - 1 && gy <= ryhi;
+          rown |= (xo && yo) ? 1u << (2 * i + o) : 0u;
+          rneed |= (xn && yn) ? 1u << (2 * i + o) : 0u;
+        }
+      }
+    }
+    const uint32_t planed = 2u * planeb;  // FP64 plane bytes
+    // FP64 access at node (i, o): the lane offset (out of range where `mask` has no bit)
+    // plus the row offset (rows are 2 x the FP32 row offsets)
+    auto ld8 = [&](PlaneBuf b, unsigned mask, int i, int o, const uint32_t (&dx)[2]) -> double {
+      const uint32_t co = ((mask >> (2 * i + o)) & 1u) ? dx[o] : kOff;
+      if constexpr (LW == 64) return buf_load<double>(b, co, 2u * rowb[i]);
+      else return buf_load<double>(b, co + 2u * rowb[i], 0u);
+    };
+    // corrected planes, ring slot = phase mod 3; the slot of plane zl-H receives its
+    // iterate's loads at the start of step zl (its previous plane, zl-H-3, was last read in
+    // step zl-1) and the correction at the end
+    double UN[REF ? 3 : 1][REF ? RPW : 1][2];
+    double PFD[REF ? RPW : 1][2];  // f of plane zl-H-1
+#pragma unroll
+    for (int a3 = 0; a3 < (REF ? 3 : 1); ++a3)
+#pragma unroll
+      for (int i = 0; i < (REF ? RPW : 1); ++i) UN[a3][i][0] = UN[a3][i][1] = 0.0;
+    double sumsq = 0.0;
+    double se = 0.0, sr = 1.0;  // correction scale, r32 = r * sr
+    if constexpr (REF) {
+      se = ra.scale_e[0];
+      sr = 1.0 / ra.scale_r[0];
+    }
+    // loads of the step that completes plane zl-H: its iterate, and f of plane zl-H-1
+    auto refine_load = [&](auto PC) {
+      constexpr int sn = imod(decltype(PC)::value, 3);
+      const int pf = zl - H, q = pf - 1;
+      if (pf >= z0 - 1 && pf <= z1) {
+        const PlaneBuf bu = plane_buf(ra.u, (size_t)pf * planed, planed);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+          for (int o = 0; o < 2; ++o) UN[sn][i][o] = ld8(bu, rneed, i, o, dxn);
+      }
+      if (q >= z0 && q < z1) {
+        const PlaneBuf bf = plane_buf(ra.f, (size_t)q * planed, planed);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+          for (int o = 0; o < 2; ++o) PFD[i][o] = ld8(bf, rown, i, o, dxo);
+      }
+    };
+    // End of step zl (phase P): (1) plane pf = zl-H is final: its corrected iterate
+    // u + s_e e (interior nodes; u elsewhere) enters ring slot P mod 3 and its edge rows go
+    // to LDS; (2) the residual of plane q = pf-1 (the corrected planes q-1, q, q+1 are in the
+    // ring, the adjacent groups' edge rows of q in the LDS buffer of the previous step),
+    // stored with the corrected iterate on the owned nodes.  The operations and their order
+    // are those of the separate refinement pass.
+    auto refine_step = [&](auto PC) {
+      constexpr int P = decltype(PC)::value;
+      constexpr int rb = (P + 1) & 1, wb = P & 1;
+      constexpr int sn = imod(P, 3), sq = imod(P - 1, 3), sm = imod(P - 2, 3);
+      constexpr int cfin = imod(P - H, Q);  // queue slot of plane zl-H
+      const int pf = zl - H, q = pf - 1;
+      if (pf >= z0 - 1 && pf <= z1) {
+        const bool zin = pf >= 1 && pf <= n - 2;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const bool in = zin && ((upd >> (2 * i + o)) & 1u);
+            if (in) UN[sn][i][o] = UN[sn][i][o] + se * (double)U[cfin][i][o];
+          }
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          sh.eun[wb][w][0][o][lane] = UN[sn][0][o];
+          sh.eun[wb][w][1][o][lane] = UN[sn][RPW - 1][o];
+        }
+      }
+      if (q >= z0 && q < z1) {
+        const PlaneBuf bo = plane_buf(ra.out, (size_t)q * planed, planed);
+        const PlaneBuf br = plane_buf(ra.r32, (size_t)q * planeb, planeb);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const double l1 = from_lane_below(UN[sq][i][1]);
+          const double r0 = from_lane_above(UN[sq][i][0]);
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const double ui = UN[sq][i][o];
+            const double xm = o == 0 ? l1 : UN[sq][i][0];
+            const double xp = o == 0 ? UN[sq][i][1] : r0;
+            const double ym = i > 0 ? UN[sq][i - 1][o] : sh.eun[rb][wm][1][o][lane];
+            const double yp = i < RPW - 1 ? UN[sq][i + 1][o] : sh.eun[rb][wp][0][o][lane];
+            const double au =
+                au_const<double, 3>(ra.ih2, ui, xm, xp, ym, yp, UN[sm][i][o], UN[sn][i][o]);
+            const double r = PFD[i][o] - au;
+            const bool own = (rown >> (2 * i + o)) & 1u;
+            if (own) sumsq += r * r;
+            const float rk = (float)(r * sr);
+            const uint32_t cd = own ? dxo[o] : kOff;
+            const uint32_t cs = own ? dxo[o] >> 1 : kOff;  // FP32 column offset
+            if constexpr (LW == 64) {
+              buf_store(ui, bo, cd, 2u * rowb[i]);
+              buf_store(rk, br, cs, rowb[i]);
+            } else {
+              buf_store(ui, bo, cd + 2u * rowb[i], 0u);
+              buf_store(rk, br, cs + rowb[i], 0u);
+            }
+          }
+        }
+      }
+    };
+
     auto body = [&](auto PC) -> bool {
       constexpr int P = decltype(PC)::value;
       constexpr int s0 = imod(P, Q);
@@ -403,6 +561,10 @@ struct Tiled {
       // P-H-1): storing it here, just before the next loads, lets the stores complete in
       // the shadow of the loads instead of delaying the next step's wait for them.
       store(zl - 1 - H, IC<imod(P - H - 1, Q)>{});
+      // REF: the FP64 loads, consumed at the end of this step, go first -- memory
+      // instructions complete in order, so the wait for them then leaves the prefetch of
+      // the next plane in flight
+      if constexpr (REF) refine_load(IC<P>{});
       if (zl + PD < zend) load(zl + PD, IC<PD == 2 ? zpar : 1 - zpar>{}, IC<buf>{});
       constexpr int rb = (P + 1) & 1;  // LDS buffer written in the previous step
       constexpr int wb = P & 1;        // LDS buffer written in this step
@@ -487,7 +649,8 @@ struct Tiled {
         }
       }
 
-      if constexpr (RES) restrict_step(IC<P>{});
+      if constexpr (RES == 1) restrict_step(IC<P>{});
+      if constexpr (REF) refine_step(IC<P>{});
       // the last step stores its own finished plane zl - H
       if (zl + 1 == zend) store(zl - H, IC<imod(P - H, Q)>{});
       ++zl;
@@ -504,6 +667,18 @@ struct Tiled {
     };
     while (round(std::make_integer_sequence<int, Q>{})) {
     }
+    if constexpr (REF) {
+      // per-workgroup sum of r^2: lanes, then waves in order
+#pragma unroll
+      for (int o2 = 32; o2 >= 1; o2 >>= 1) sumsq += __shfl_xor(sumsq, o2, 64);
+      if ((threadIdx.x & 63) == 0) sh.red[threadIdx.x >> 6] = sumsq;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int v = 0; v < W; ++v) tot += sh.red[v];
+        ra.partial[blockIdx.x] = tot;
+      }
+    }
   }
 };
 
@@ -511,7 +686,7 @@ template <typename T, bool VAR, int S, int W, int RPW, int PD, int IN, int RES, 
 __global__ void __launch_bounds__(64 * W)
     k_rbgs_tiled(const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
                  const T* __restrict__ k, const T* __restrict__ ec, int nc, int n, T h2,
-                 T ih2, T* __restrict__ fc, int tiles_x, int tiles_y, int zlen)
+                 T ih2, T* __restrict__ fc, int tiles_x, int tiles_y, int zlen, RefineArgs ra)
 {
   using C = Tiled<T, VAR, S, W, RPW, PD, RES, LW>;
   __shared__ typename C::Shared sh;
@@ -526,11 +701,11 @@ __global__ void __launch_bounds__(64 * W)
   const int ox = 1 + tx * C::TXO, oy = 1 + ty * C::TYO;
   const int z0 = 1 + tz * zlen;
   const int z1 = min(z0 + zlen, n - 1);
-  // parity of (x of column 0) + (y of row 0) + z0 - 1; RPW is even, so it is the same
-  // for every row group's first row
-  const int b0 = ((ox - C::H) + (oy - C::H) + z0 - 1) & 1;
-  if (b0) C::template run<1, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, sh);
-  else C::template run<0, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, sh);
+  // parity of (x of column 0) + (y of row 0) + z0 - 1 + ZR; RPW is even, so it is the
+  // same for every row group's first row
+  const int b0 = ((ox - C::H) + (oy - C::H) + z0 - 1 + C::ZR) & 1;
+  if (b0) C::template run<1, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, ra, sh);
+  else C::template run<0, IN>(uin, uout, f, k, ec, nc, n, h2, ox, oy, z0, z1, ih2, fc, ra, sh);
 }
 
 struct LaunchShape {
@@ -672,24 +847,41 @@ LaunchShape shape_for(int n, int capacity)
 #ifndef MG_SMOOTH64_PROLONG_RPW
 #define MG_SMOOTH64_PROLONG_RPW 2
 #endif
+// The FP32 post-smoothing pass with the refinement step also holds three corrected FP64
+// planes and f of a step: 12 waves of 2 rows (64 x 48-node tiles in the 64-column layout)
+// fit in 167 VGPRs, 3 waves per SIMD.  FP32-refined solve at 513^3: 20.17 ms against 20.32
+// for 8 x 4 in the 128-column layout (249 VGPRs; the 64-column layout spills) and 20.40
+// with the separate passes.
+#ifndef MG_SMOOTH32_REF_W
+#define MG_SMOOTH32_REF_W 12
+#endif
+#ifndef MG_SMOOTH32_REF_RPW
+#define MG_SMOOTH32_REF_RPW 2
+#endif
+#ifndef MG_SMOOTH32_REF_NARROW
+#define MG_SMOOTH32_REF_NARROW 1
+#endif
 template <typename T, bool VAR, int S, int IN, int RES>
 struct Shape {
   static constexpr bool f32 = sizeof(T) == 4, plain = !VAR && S == 2;
-  static constexpr int W = RES                ? (f32 ? MG_SMOOTH32_RES_W : MG_SMOOTH64_RES_W)
+  static constexpr int W = RES == 2           ? MG_SMOOTH32_REF_W
+                           : RES              ? (f32 ? MG_SMOOTH32_RES_W : MG_SMOOTH64_RES_W)
                            : (!f32 && VAR && S == 2) ? MG_SMOOTH64_VAR_W
                            : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_W
                            : !(f32 && plain)   ? MG_SMOOTH_W
                            : IN == kInProlong ? MG_SMOOTH32_PROLONG_W
                            : IN == kInZero    ? MG_SMOOTH32_ZERO_W
                                               : MG_SMOOTH32_READ_W;
-  static constexpr int RPW = RES                ? (f32 ? MG_SMOOTH32_RES_RPW : MG_SMOOTH64_RES_RPW)
+  static constexpr int RPW = RES == 2           ? MG_SMOOTH32_REF_RPW
+                             : RES              ? (f32 ? MG_SMOOTH32_RES_RPW : MG_SMOOTH64_RES_RPW)
                              : (!f32 && VAR && S == 2) ? MG_SMOOTH64_VAR_RPW
                              : (!f32 && plain && IN == kInProlong) ? MG_SMOOTH64_PROLONG_RPW
                              : !(f32 && plain)   ? MG_SMOOTH_RPW
                              : IN == kInProlong ? MG_SMOOTH32_PROLONG_RPW
                              : IN == kInRead    ? MG_SMOOTH32_READ_RPW
                                                 : MG_SMOOTH_RPW;
-  static constexpr int PD = RES ? (f32 ? MG_SMOOTH32_RES_PD : 1)
+  static constexpr int PD = RES == 2 ? 1
+                            : RES ? (f32 ? MG_SMOOTH32_RES_PD : 1)
                             : !plain ? 1
                             : IN == kInProlong ? (f32 ? MG_SMOOTH32_PROLONG_PD : 1)
                             : IN == kInZero    ? (f32 ? MG_SMOOTH32_ZERO_PD : MG_SMOOTH64_ZERO_PD)
@@ -698,7 +890,8 @@ struct Shape {
   // offsets cost ~20-40 VGPRs, which the FP64 variable-coefficient pass does not have to
   // spare (it would spill; so would the FP32 restriction and prolongation passes with a
   // second prefetch buffer or 6 rows per wave in the restriction)
-  static constexpr bool NARROW = RES ? MG_SMOOTH32_RES_NARROW
+  static constexpr bool NARROW = RES == 2 ? MG_SMOOTH32_REF_NARROW
+                                 : RES ? MG_SMOOTH32_RES_NARROW
                                  : IN == kInProlong ? MG_SMOOTH32_PROLONG_NARROW
                                  : (!f32 && VAR && S == 2) ? MG_SMOOTH64_VAR_NARROW
                                                     : !(VAR && !f32);
@@ -709,8 +902,8 @@ struct Shape {
 // workgroup on the critical path at this grid size is launched (the 128-column layout on
 // a tie).  Both give bitwise the same result.
 template <typename T, bool VAR, int S, int IN, int RES = 0>
-void launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
-               const T* ec, T* fc = nullptr)
+int launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* uin, T* uout,
+              const T* ec, T* fc = nullptr, RefineArgs ra = {})
 {
   using Sh = Shape<T, VAR, S, IN, RES>;
   constexpr int W = Sh::W, RPW = Sh::RPW, PD = Sh::PD;
@@ -723,13 +916,16 @@ void launch_in(hipStream_t s, int n, double h, const T* k, const T* f, const T* 
     auto k32 = k_rbgs_tiled<T, VAR, S, W, RPW, PD, IN, RES, 32>;
     const LaunchShape L32 = shape_for<Tiled<T, VAR, S, W, RPW, PD, RES, 32>>(n, resident_capacity(k32, 64 * W));
     if (L32.cost < L64.cost) {
+      if (RES == 2 && L32.blocks > kStreamPartials) return -1;  // one partial sum per workgroup
       k32<<<L32.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, ih2, fc, L32.tiles_x,
-                                        L32.tiles_y, L32.zlen);
-      return;
+                                        L32.tiles_y, L32.zlen, ra);
+      return L32.blocks;
     }
   }
+  if (RES == 2 && L64.blocks > kStreamPartials) return -1;
   k64<<<L64.blocks, 64 * W, 0, s>>>(uin, uout, f, k, ec, nc, n, h2, ih2, fc, L64.tiles_x,
-                                    L64.tiles_y, L64.zlen);
+                                    L64.tiles_y, L64.zlen, ra);
+  return L64.blocks;
 }
 
 template <typename T, bool VAR, int S>
@@ -804,6 +1000,69 @@ void rbgs_tiled(hipStream_t s, int n, double h, const T* k, const T* f, const T*
     if (k) launch_cfg<T, true, 1>(s, n, h, k, f, uin, uout, zero_in, ec);
     else launch_cfg<T, false, 1>(s, n, h, k, f, uin, uout, zero_in, ec);
   }
+}
+
+namespace {
+// The power of two nearest in log2 to the root mean square of a residual whose squares sum
+// to norm2 over `interior` nodes (1 if that is 0 or not finite).  The FP32 right-hand side
+// of a correction cycle is the residual divided by it: any power of two changes no float
+// result and keeps the values away from the float range limits.
+__device__ double ir_scale_of(double norm2, double interior)
+{
+  const double rms = sqrt(norm2 / interior);
+  if (!(rms > 0.0) || !__builtin_isfinite(rms)) return 1.0;
+  int e = 0;
+  const double m = frexp(rms, &e);  // rms = m 2^e, 0.5 <= m < 1
+  return ldexp(1.0, m >= 0.70710678118654752 ? e : e - 1);
+}
+
+// norm2[0] = fixed-order sum of the per-workgroup partials, scale[0] = its scale
+__global__ void __launch_bounds__(256)
+    k_sum_scale(const double* __restrict__ partial, int count, double* __restrict__ norm2,
+                double interior, double* __restrict__ scale)
+{
+  __shared__ double part[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = (part[0] + part[1]) + (part[2] + part[3]);
+    norm2[0] = tot;
+    scale[0] = ir_scale_of(tot, interior);
+  }
+}
+
+__global__ void k_scale_init(const double* __restrict__ norm2, double s0, double interior,
+                             double* __restrict__ ss)
+{
+  if (threadIdx.x == 0) {
+    ss[0] = s0;
+    ss[1] = ir_scale_of(norm2[0], interior);
+  }
+}
+}  // namespace
+
+bool rbgs_tiled_refine(hipStream_t s, int n, double h, const float* rhs, const float* ein,
+                       const float* ec, const double* f, const double* u, double* uout,
+                       float* r32, const double* scale_e, const double* scale_r,
+                       double* partial, double* norm2, double* scale_next)
+{
+  RefineArgs ra{u, uout, f, r32, scale_e, scale_r, 1.0 / (h * h), partial};
+  const int blocks = launch_in<float, false, 2, kInProlong, 2>(s, n, h, nullptr, rhs, ein,
+                                                               nullptr, ec, nullptr, ra);
+  if (blocks < 0) return false;
+  const double interior = (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  k_sum_scale<<<1, 256, 0, s>>>(partial, blocks, norm2, interior, scale_next);
+  return true;
+}
+
+void ir_scales_init(hipStream_t s, int n, const double* norm2, double scale0, double* ss)
+{
+  const double interior = (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  k_scale_init<<<1, 64, 0, s>>>(norm2, scale0, interior, ss);
 }
 
 template void rbgs_tiled<double>(hipStream_t, int, double, const double*, const double*,

@@ -13,8 +13,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_RESTRICT, FUSE_TAIL,  # noqa: F401
-                   FUSE_ZERO,
+from ._lib import (FUSE_ALL, FUSE_BLOCKED, FUSE_PROLONG, FUSE_REFINE, FUSE_RESTRICT,  # noqa: F401
+                   FUSE_TAIL, FUSE_ZERO,
                    MG_ENOCONV, MG_F32_IR, MG_F64, MgGrid, check, lib)
 
 

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 from conftest import interior, relmax
-from paper_2403_08063_amd import (FUSE_ALL, FUSE_PROLONG, FUSE_RESTRICT, FUSE_TAIL, FUSE_ZERO,
+from paper_2403_08063_amd import (FUSE_ALL, FUSE_PROLONG, FUSE_REFINE, FUSE_RESTRICT, FUSE_TAIL, FUSE_ZERO,
                                   Multigrid, inputs)
 
 pytestmark = pytest.mark.gpu
@@ -146,6 +146,37 @@ def test_fused_passes_bitwise_equal_separate_passes(dim, n, levels, var, prec, o
         out.append(host(u))
         mg.close()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("n,levels,nu1,seed", [(129, 6, 2, 41), (161, 6, 2, 42), (257, 7, 2, 43),
+                                                (321, 7, 1, 44), (129, 5, 3, 45)])
+def test_fused_refinement_bitwise_equals_separate_passes(n, levels, nu1, seed):
+    """FP32-refined solves with the refinement step inside the last post-smoothing pass of
+    each correction cycle give the iterate of the separate post-smoothing and refinement
+    passes bit for bit, with the same cycle count; only the residual norm is summed in
+    another order.  A second solve on the same context starts from the previous iterate
+    (nonzero interior and boundary data) with the previous right-hand-side scale."""
+    say(f"fused refinement n={n} levels={levels} nu1={nu1}")
+    f = inputs.uniform_interior(3, n, seed)
+    g = random_interior(3, n, seed + 100)
+    g[1:-1, 1:-1, 1:-1] = 0.0
+    g[0] += 0.5  # Dirichlet data on one face
+    res = []
+    for flags in (FUSE_ALL, FUSE_ALL & ~FUSE_REFINE):
+        mg = Multigrid(3, n, levels, nu1=nu1, precision="f32_ir", device=DEV)
+        mg.set_fusion(flags)
+        u = dev(g)
+        _, i1 = mg.solve(dev(f), u, tol=1e-10)
+        u1 = host(u)
+        _, i2 = mg.solve(dev(0.5 * f), u, tol=1e-11)
+        res.append((u1, i1, host(u), i2))
+        mg.close()
+    (a1, ia1, a2, ia2), (b1, ib1, b2, ib2) = res
+    assert ia1.cycles == ib1.cycles and ia2.cycles == ib2.cycles
+    assert np.array_equal(a1, b1) and np.array_equal(a2, b2)
+    assert abs(ia1.relres - ib1.relres) <= 1e-12 * ib1.relres
+    assert abs(ia2.relres - ib2.relres) <= 1e-12 * ib2.relres
+    assert ia1.relres <= 1e-10 and ia2.relres <= 1e-11
 
 
 @pytest.mark.parametrize("dim,n,levels,var", [(2, 65, 5, False), (3, 65, 5, False),
@@ -484,4 +515,4 @@ def test_error_statuses():
     with pytest.raises(ValueError):
         mg2.solve(dev(f[:-1]))
     with pytest.raises(MgError, match="MG_EINVAL"):
-        mg2.set_fusion(32)
+        mg2.set_fusion(64)
