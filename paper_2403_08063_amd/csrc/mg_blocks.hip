@@ -288,11 +288,14 @@ __device__ __forceinline__ int tangential_first(int order, int T, int B, int t)
 }
 
 // value of the interface ghost cell (t1, t2) of face (ax, side) with face-table entry e (kind
-// same, F2C or C2F), from the neighbouring blocks' inner cells read through rd(b, z, y, x)
-template <class Rd>
-__device__ __forceinline__ double interface_ghost(const Rd& rd, int B, int order, const C2FWeights& W,
+// same, F2C or C2F), from the neighbouring blocks' inner cells read through rd(b, z, y, x).
+// The C2F order is a compile-time constant, so that the (order+1)^3 terms unroll and their
+// loads are issued together instead of one round trip after another.
+template <int ORDER, class Rd>
+__device__ __forceinline__ double interface_ghost(const Rd& rd, int B, const C2FWeights& W,
                                                   const int* e, int ax, int side, int t1, int t2)
 {
+  constexpr int order = ORDER;
   const int kind = e[0];
   if (kind == kFaceSame) {
     int x, y, z;
@@ -322,11 +325,14 @@ __device__ __forceinline__ double interface_ghost(const Rd& rd, int B, int order
   const int a1 = tangential_first(order, T1, B, p1), a2 = tangential_first(order, T2, B, p2);
   const double* w1 = W.wt[a1 + 2][p1];
   const double* w2 = W.wt[a2 + 2][p2];
-  const int cn = order + 1;
+  constexpr int cn = order + 1;
   const int ci = side ? 1 : B, away = side ? 1 : -1;
   double s = 0.0;
+#pragma unroll
   for (int a = 0; a < cn; ++a)  // normal bases 0, -1, -2: away from the interface
+#pragma unroll
     for (int j2 = 0; j2 < cn; ++j2)
+#pragma unroll
       for (int j1 = 0; j1 < cn; ++j1) {
         int x, y, z;
         face_coords(ax, ci + away * a, T1 + 1 + a1 + j1, T2 + 1 + a2 + j2, x, y, z);
@@ -339,7 +345,8 @@ constexpr int kFillThreads = 256;
 
 // ghost cell q (0 .. B^2-1) of face f of block b: filled by its rule unless the face lies on
 // the domain boundary
-__device__ __forceinline__ void fill_ghost(int B, int order, const C2FWeights& W,
+template <int ORDER>
+__device__ __forceinline__ void fill_ghost(int B, const C2FWeights& W,
                                            const int* __restrict__ faces, double* __restrict__ u,
                                            int q, int f, int b)
 {
@@ -350,15 +357,16 @@ __device__ __forceinline__ void fill_ghost(int B, int order, const C2FWeights& W
   int gx, gy, gz;
   face_coords(f >> 1, (f & 1) ? B + 1 : 0, t1, t2, gx, gy, gz);
   auto rd = [&](int bb, int z, int y, int x) { return u[bidx(m, bb, z, y, x)]; };
-  u[bidx(m, b, gz, gy, gx)] = interface_ghost(rd, B, order, W, e, f >> 1, f & 1, t1, t2);
+  u[bidx(m, b, gz, gy, gx)] = interface_ghost<ORDER>(rd, B, W, e, f >> 1, f & 1, t1, t2);
 }
 
+template <int ORDER>
 __global__ void __launch_bounds__(kFillThreads)
-    k_blk_fill(int B, int order, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
+    k_blk_fill(int B, C2FWeights W, const int* __restrict__ faces, double* __restrict__ u)
 {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;  // ghost cell of the face
   if (q >= B * B) return;
-  fill_ghost(B, order, W, faces, u, q, blockIdx.y, blockIdx.z);
+  fill_ghost<ORDER>(B, W, faces, u, q, blockIdx.y, blockIdx.z);
 }
 
 // (A u) at inner cell (z, y, x) of block b from the six stored neighbours: interface ghosts
@@ -467,6 +475,37 @@ __global__ void __launch_bounds__(kCellThreads)
   int b, z, y, x;
   if (!cell_of(B, b, z, y, x)) return;
   jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, z, y, x);
+}
+
+// Damped-Jacobi sweep of a level of small blocks (B <= kSmallB) in one launch, one workgroup
+// per block: workgroup b fills block b's interface ghosts of u from the neighbouring blocks'
+// inner cells (which no workgroup writes in this launch), then, after a barrier, sweeps
+// block b's inner cells into uout.  Same values as k_blk_fill followed by k_blk_jacobi, in
+// one launch instead of two: on the coarsest level, whose 256 iterations are launch-bound,
+// that halves the launches.
+constexpr int kSmallB = 16;
+constexpr int kSmallThreadsMax = 1024;
+int small_threads(int B)
+{
+  const int work = 6 * B * B > B * B * B ? 6 * B * B : B * B * B;
+  const int t = (work + 63) / 64 * 64;
+  return t < kSmallThreadsMax ? t : kSmallThreadsMax;
+}
+
+template <int ORDER>
+__global__ void __launch_bounds__(kSmallThreadsMax)
+    k_blk_sweep_small(int B, C2FWeights W, double omega, const int* __restrict__ faces,
+                      const double* __restrict__ hs, const double* __restrict__ f, double* u,
+                      double* __restrict__ uout, int coarse)
+{
+  const int b = blockIdx.x;
+  const int nf = B * B, n3 = nf * B;
+  for (int g = threadIdx.x; g < 6 * nf; g += blockDim.x) fill_ghost<ORDER>(B, W, faces, u, g % nf, g / nf, b);
+  __syncthreads();
+  for (int t = threadIdx.x; t < n3; t += blockDim.x) {
+    const int zz = t / nf, r = t - zz * nf, yy = r / B;
+    jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, 1 + zz, 1 + yy, 1 + r - yy * B);
+  }
 }
 
 // Damped-Jacobi sweep of blocks of >= 64 cells a side, marching along z: a thread owns
@@ -759,7 +798,11 @@ dim3 face_grid(int B)
 void fill(mgblk_ctx* c, int l, double* u)
 {
   const int B = c->lv[l].B;
-  k_blk_fill<<<face_grid(B), face_threads(B), 0, c->s>>>(B, c->g.order, c->w, c->faces, u);
+  const dim3 g = face_grid(B);
+  const int t = face_threads(B);
+  if (c->g.order == 0) k_blk_fill<0><<<g, t, 0, c->s>>>(B, c->w, c->faces, u);
+  else if (c->g.order == 1) k_blk_fill<1><<<g, t, 0, c->s>>>(B, c->w, c->faces, u);
+  else k_blk_fill<2><<<g, t, 0, c->s>>>(B, c->w, c->faces, u);
 }
 
 void copy_boundary(mgblk_ctx* c, int l, const double* src, double* dst)
@@ -778,6 +821,16 @@ double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, i
   const bool zrun = B >= kCellRowsMin && B % kZRun == 0;
   const dim3 zgrid((unsigned)((B + 63) / 64), (unsigned)((B + 3) / 4), (unsigned)(kBlocks * (B / kZRun)));
   for (int s = 0; s < count; ++s) {
+    if (B <= kSmallB) {
+      auto k = c->g.order == 0 ? k_blk_sweep_small<0>
+               : c->g.order == 1 ? k_blk_sweep_small<1> : k_blk_sweep_small<2>;
+      k<<<kBlocks, small_threads(B), 0, c->s>>>(B, c->w, c->g.omega, c->faces, L.hs, f, cur, oth,
+                                                l > 0);
+      double* x = cur;
+      cur = oth;
+      oth = x;
+      continue;
+    }
     fill(c, l, cur);
     if (zrun)
       k_blk_jacobi_z<<<zgrid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
