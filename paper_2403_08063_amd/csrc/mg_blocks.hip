@@ -467,14 +467,31 @@ __device__ __forceinline__ void jacobi_cell(int B, double omega, const int* __re
   uout[i] = u[i] + omega * (h * h / 6.0) * (f[i] - au);
 }
 
+// jacobi_cell of an identically zero u: the same operations on literal zeros (the ghost
+// values of a zero u are 0 too: linear rules, and a zero Dirichlet g on a coarse level)
+__device__ __forceinline__ void jacobi_cell_zero(int B, double omega,
+                                                 const double* __restrict__ hs,
+                                                 const double* __restrict__ f,
+                                                 double* __restrict__ uout, bool coarse, int b,
+                                                 int z, int y, int x)
+{
+  const int m = B + 2;
+  const double h = hs[b];
+  const size_t i = bidx(m, b, z, y, x);
+  const double zero[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const double au = blk_apply_vals(1.0 / (h * h), 0.0, zero, 0u, coarse);
+  uout[i] = 0.0 + omega * (h * h / 6.0) * (f[i] - au);
+}
+
 __global__ void __launch_bounds__(kCellThreads)
     k_blk_jacobi(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
                  const double* __restrict__ f, const double* __restrict__ u, double* __restrict__ uout,
-                 int coarse)
+                 int coarse, int zero)
 {
   int b, z, y, x;
   if (!cell_of(B, b, z, y, x)) return;
-  jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, z, y, x);
+  if (zero) jacobi_cell_zero(B, omega, hs, f, uout, coarse != 0, b, z, y, x);
+  else jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, z, y, x);
 }
 
 // Damped-Jacobi sweep of a level of small blocks (B <= kSmallB) in one launch, one workgroup
@@ -492,7 +509,9 @@ int small_threads(int B)
   return t < kSmallThreadsMax ? t : kSmallThreadsMax;
 }
 
-template <int ORDER>
+// ZERO: u is identically 0 (a coarse level's initial correction; not read, its ghosts not
+// filled): each cell takes jacobi_cell's formula on literal zeros.
+template <int ORDER, bool ZERO>
 __global__ void __launch_bounds__(kSmallThreadsMax)
     k_blk_sweep_small(int B, C2FWeights W, double omega, const int* __restrict__ faces,
                       const double* __restrict__ hs, const double* __restrict__ f, double* u,
@@ -500,11 +519,14 @@ __global__ void __launch_bounds__(kSmallThreadsMax)
 {
   const int b = blockIdx.x;
   const int nf = B * B, n3 = nf * B;
-  for (int g = threadIdx.x; g < 6 * nf; g += blockDim.x) fill_ghost<ORDER>(B, W, faces, u, g % nf, g / nf, b);
-  __syncthreads();
+  if (!ZERO) {
+    for (int g = threadIdx.x; g < 6 * nf; g += blockDim.x) fill_ghost<ORDER>(B, W, faces, u, g % nf, g / nf, b);
+    __syncthreads();
+  }
   for (int t = threadIdx.x; t < n3; t += blockDim.x) {
     const int zz = t / nf, r = t - zz * nf, yy = r / B;
-    jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, 1 + zz, 1 + yy, 1 + r - yy * B);
+    if (ZERO) jacobi_cell_zero(B, omega, hs, f, uout, coarse != 0, b, 1 + zz, 1 + yy, 1 + r - yy * B);
+    else jacobi_cell(B, omega, faces, hs, f, u, uout, coarse != 0, b, 1 + zz, 1 + yy, 1 + r - yy * B);
   }
 }
 
@@ -520,7 +542,7 @@ constexpr int kZRun = MG_BLK_ZRUN;
 __global__ void __launch_bounds__(kCellThreads)
     k_blk_jacobi_z(int B, double omega, const int* __restrict__ faces, const double* __restrict__ hs,
                    const double* __restrict__ f, const double* __restrict__ u,
-                   double* __restrict__ uout, int coarse)
+                   double* __restrict__ uout, int coarse, int zero)
 {
   const int x = 1 + blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = 1 + blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -539,6 +561,17 @@ __global__ void __launch_bounds__(kCellThreads)
                        (y == B && fb[3 * kFaceInts] == kFaceBoundary ? 8u : 0u);
   const bool zlo = fb[4 * kFaceInts] == kFaceBoundary, zhi = fb[5 * kFaceInts] == kFaceBoundary;
   size_t i = bidx(m, b, z0, y, x);
+  if (zero) {
+    // u identically 0 (a coarse level's initial correction): the formula on literal zeros
+    for (int k = 0; k < kZRun; ++k, i += sz) {
+      const int z = z0 + k;
+      const double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      const unsigned bnd = bxy | (z == 1 && zlo ? 16u : 0u) | (z == B && zhi ? 32u : 0u);
+      const double au = blk_apply_vals(ih2, 0.0, v, bnd, coarse != 0);
+      uout[i] = 0.0 + coef * (f[i] - au);
+    }
+    return;
+  }
   double zm = u[i - sz], c = u[i];
   for (int k = 0; k < kZRun; ++k, i += sz) {
     const int z = z0 + k;
@@ -652,7 +685,11 @@ __global__ void __launch_bounds__(kCellThreads)
   u[i] = u[i] + 0.25 * (((eP + ex) + ey) + ez);
 }
 
-// Residual restriction for fine blocks of >= 128 cells a side (coarse >= 64), marching along
+#ifndef MG_BLK_RESTRICT_Z_MIN
+#define MG_BLK_RESTRICT_Z_MIN 32
+#endif
+constexpr int kRestrictZMin = MG_BLK_RESTRICT_Z_MIN;
+// Residual restriction for fine blocks of >= 2 kRestrictZMin cells a side, marching along
 // z: a thread owns coarse column (X, Y) of a 64 x 4 coarse tile for kZRun coarse planes and
 // keeps the 2 x 2 fine columns of the planes 2Z .. 2Z+3 it needs in registers (the upper two
 // are the next coarse plane's lower two).  Per child the operations of k_blk_restrict, summed
@@ -812,8 +849,11 @@ void copy_boundary(mgblk_ctx* c, int l, const double* src, double* dst)
 }
 
 // `count` sweeps on level l with a fill before each, alternating between cur and oth (which
-// holds the same domain-boundary ghosts); returns the buffer holding the result
-double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, int count)
+// holds the same domain-boundary ghosts); returns the buffer holding the result.  zero: cur is
+// identically 0 (a coarse level's initial correction, l > 0): the first sweep reads neither
+// it nor its ghosts, and needs no fill (same values).
+double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, int count,
+               bool zero = false)
 {
   const BlkLevel& L = c->lv[l];
   const int B = L.B;
@@ -821,9 +861,11 @@ double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, i
   const bool zrun = B >= kCellRowsMin && B % kZRun == 0;
   const dim3 zgrid((unsigned)((B + 63) / 64), (unsigned)((B + 3) / 4), (unsigned)(kBlocks * (B / kZRun)));
   for (int s = 0; s < count; ++s) {
+    const bool z0 = zero && s == 0 && l > 0;
     if (B <= kSmallB) {
-      auto k = c->g.order == 0 ? k_blk_sweep_small<0>
-               : c->g.order == 1 ? k_blk_sweep_small<1> : k_blk_sweep_small<2>;
+      auto k = c->g.order == 0 ? (z0 ? k_blk_sweep_small<0, true> : k_blk_sweep_small<0, false>)
+               : c->g.order == 1 ? (z0 ? k_blk_sweep_small<1, true> : k_blk_sweep_small<1, false>)
+                                 : (z0 ? k_blk_sweep_small<2, true> : k_blk_sweep_small<2, false>);
       k<<<kBlocks, small_threads(B), 0, c->s>>>(B, c->w, c->g.omega, c->faces, L.hs, f, cur, oth,
                                                 l > 0);
       double* x = cur;
@@ -831,11 +873,13 @@ double* sweeps(mgblk_ctx* c, int l, const double* f, double* cur, double* oth, i
       oth = x;
       continue;
     }
-    fill(c, l, cur);
+    if (!z0) fill(c, l, cur);
     if (zrun)
-      k_blk_jacobi_z<<<zgrid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
+      k_blk_jacobi_z<<<zgrid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0,
+                                                       z0);
     else
-      k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0);
+      k_blk_jacobi<<<grid, kCellThreads, 0, c->s>>>(B, c->g.omega, c->faces, L.hs, f, cur, oth, l > 0,
+                                                    z0);
     double* x = cur;
     cur = oth;
     oth = x;
@@ -849,7 +893,10 @@ void restrict_residual(mgblk_ctx* c, int l, const double* f, double* u, double* 
   const BlkLevel& L = c->lv[l];
   const int Bc = L.B / 2;
   fill(c, l, u);
-  if (Bc >= kCellRowsMin && Bc % kZRun == 0)
+  // the plane-marching kernel from 32 coarse cells a side on (its 64 x 4 tile then leaves
+  // half the lanes idle, but marching in z still beats one thread per coarse cell: 64^3 ->
+  // 32^3 in about 0.15 ms instead of 0.24)
+  if (Bc >= kRestrictZMin && Bc % kZRun == 0)
     k_blk_restrict_z<<<dim3((unsigned)((Bc + 63) / 64), (unsigned)((Bc + 3) / 4),
                             (unsigned)(kBlocks * (Bc / kZRun))),
                        kCellThreads, 0, c->s>>>(L.B, c->faces, L.hs, f, u, fc, uc, l > 0);
@@ -872,15 +919,18 @@ void prolong_correct(mgblk_ctx* c, int l, double* ec, double* u)
 
 // V(nu1, nu2) on level l from the iterate in x (y: the level's second buffer); returns the
 // buffer holding the result.  Coarse problems start from 0 in the level's u.
-double* vcycle_rec(mgblk_ctx* c, int l, const double* f, double* x, double* y)
+double* vcycle_rec(mgblk_ctx* c, int l, const double* f, double* x, double* y, bool zero = false)
 {
   const int last = (int)c->lv.size() - 1;
-  if (l == last) return sweeps(c, l, f, x, y, c->g.coarse_iters);
-  double* cur = sweeps(c, l, f, x, y, c->g.nu1);
+  if (l == last) return sweeps(c, l, f, x, y, c->g.coarse_iters, zero);
+  double* cur = sweeps(c, l, f, x, y, c->g.nu1, zero);
   double* oth = cur == x ? y : x;
   BlkLevel& C = c->lv[l + 1];
-  restrict_residual(c, l, f, cur, C.f, C.u);
-  double* ec = vcycle_rec(c, l + 1, C.f, C.u, C.t);
+  // the coarse level starts from a zero correction: read as 0 by its first sweep, or, when
+  // its first step is not a sweep, written by the restriction
+  const bool czero = (l + 1 == last ? c->g.coarse_iters : c->g.nu1) > 0;
+  restrict_residual(c, l, f, cur, C.f, czero ? nullptr : C.u);
+  double* ec = vcycle_rec(c, l + 1, C.f, C.u, C.t, czero);
   prolong_correct(c, l, ec, cur);
   return sweeps(c, l, f, cur, oth, c->g.nu2);
 }
