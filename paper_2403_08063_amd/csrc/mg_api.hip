@@ -463,12 +463,9 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
   const bool fused_rhs = !(bn > 0);
   // The correction cycle's last pass may also apply the correction and form the next
   // residual (refine_fusable): the speculative cycle below then writes the iterate (out of
-  // place) and the scales of the right-hand sides live on the device.  A first pass that
-  // may have to be repeated with another scale (fused_rhs) is then not overlapped, since
-  // its repetition reads the buffer that such a cycle writes.
+  // place, into `other`) and the scales of the right-hand sides live on the device.
   const bool fused = refine_fusable(c);
   FusedIr fst{L0.f32, L0.u32, L0.t32, 0};
-  bool no_spec = fused && fused_rhs;
   double scale = ir_scale(c, fused_rhs ? c->last_bn : bn);  // scale of the r32 being written
   double rn2 = 0;
   const bool overlap = c->hnorm != nullptr && c->ev != nullptr;
@@ -489,7 +486,7 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
       return s2;
     }
     mg_status s2 = read_scalar_start(c, c->scal, count);
-    if (!s2 && !no_spec && predicted > 4.0 * tol && c->g.max_cycles > 0) {
+    if (!s2 && predicted > 4.0 * tol && c->g.max_cycles > 0) {
       if (fused) {
         s2 = fused_ir_cycle(c, f, cur, other, fst);
         spec = fst.rhs;  // marks the cycle as enqueued
@@ -498,7 +495,6 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
         s2 = launch_check(c, "V-cycle");
       }
     }
-    no_spec = false;
     if (!s2) s2 = read_scalar_finish(c, out, count);
     return s2;
   };
@@ -511,9 +507,10 @@ mg_status solve_ir_streamed(mg_ctx* c, const double* f, double* u, double tol, d
     const double ideal = ir_scale(c, bn);
     if (!st && (ideal / scale > 0x1p40 || scale / ideal > 0x1p40)) {
       // redo the first pass with the right scale (its r32 feeds the first cycle: a cycle
-      // enqueued ahead is discarded)
+      // enqueued ahead is discarded, with its buffer rotation).  It reads the first pass's
+      // output, a copy of the iterate: a cycle enqueued ahead may have written `other`.
       spec = nullptr;
-      std::swap(cur, other);
+      fst = FusedIr{L0.f32, L0.u32, L0.t32, 0};
       scale = ideal;
       mgk::ir_pass_tiled(c->s, L0.n, L0.h, L0.k, f, cur, nullptr, 0.0, 1.0 / scale, other,
                          L0.f32, c->partial, c->scal);
