@@ -37,7 +37,9 @@
 #include "mg_lanes.h"
 #include "mg_stencil.h"
 
+#include <mutex>
 #include <utility>
+#include <vector>
 
 namespace mgk {
 namespace {
@@ -713,24 +715,35 @@ struct LaunchShape {
   long long cost;  // rounds of resident workgroups x planes per workgroup
 };
 
-// Workgroups of this kernel that fit on the device at once (CUs x resident per CU),
-// queried once per device.
+// Workgroups of this kernel that fit on the device at once (CUs x resident per CU), queried
+// once per device, kernel and block size (every instantiation of k_rbgs_tiled has the same
+// function type, so the kernel's address is part of the key).
 template <typename Kernel>
 int resident_capacity(Kernel kernel, int block)
 {
-  static int cache[64] = {0};
+  struct Entry {
+    const void* k;
+    int block, dev, cap;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (cache[dev] == 0) {
-    int cus = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
-        per_cu <= 0)
-      per_cu = 1;
-    cache[dev] = cus * per_cu;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (const Entry& e : cache)
+      if (e.k == key && e.block == block && e.dev == dev) return e.cap;
   }
-  return cache[dev];
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  std::lock_guard<std::mutex> g(mu);
+  cache.push_back({key, block, dev, cus * per_cu});
+  return cus * per_cu;
 }
 
 // Tiles cover the interior in x and y; z is cut into chunks.  Each chunk costs its length
