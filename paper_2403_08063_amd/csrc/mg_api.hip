@@ -392,11 +392,13 @@ mg_status read_scalar_finish(mg_ctx* c, double* host, int count = 1)
 
 // Whether the FP32 correction cycle's last level-0 post-smoothing pass can also perform the
 // refinement step (rbgs_tiled_refine): a blocked level 0 with a constant coefficient, one
-// 2-sweep post-smoothing pass that takes the coarse-grid correction.
+// 2-sweep post-smoothing pass that takes the coarse-grid correction, and a launch whose
+// workgroups' partial sums fit the partial-sum buffer.
 bool refine_fusable(const mg_ctx* c)
 {
   return (c->fuse & MG_FUSE_REFINE) && (c->fuse & MG_FUSE_PROLONG) && use_tiled(c, 0) &&
-         !c->g.variable && c->g.nu2 == 2 && mgk::rbgs_tiled_max_sweeps(false, 4) == 2;
+         !c->g.variable && c->g.nu2 == 2 && mgk::rbgs_tiled_max_sweeps(false, 4) == 2 &&
+         mgk::rbgs_tiled_refine_fits(c->lv[0].n);
 }
 
 // Level-0 FP32 buffers of a fused solve: the cycle's right-hand side and the two buffers of

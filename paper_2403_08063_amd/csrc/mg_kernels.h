@@ -59,6 +59,8 @@ bool rbgs_tiled_refine(hipStream_t s, int n, double h, const float* rhs, const f
                        const float* ec, const double* f, const double* u, double* uout,
                        float* r32, const double* scale_e, const double* scale_r,
                        double* partial, double* norm2, double* scale_next);
+// Whether rbgs_tiled_refine's launch at n nodes a side fits its partial sums.
+bool rbgs_tiled_refine_fits(int n);
 // ss[0] = scale0, ss[1] = the scale (as rbgs_tiled_refine's scale_next) of the residual whose
 // squares sum to norm2[0]: the scales of the first two right-hand sides of a fused solve.
 void ir_scales_init(hipStream_t s, int n, const double* norm2, double scale0, double* ss);

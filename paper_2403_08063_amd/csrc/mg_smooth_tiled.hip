@@ -1076,6 +1076,22 @@ bool rbgs_tiled_refine(hipStream_t s, int n, double h, const float* rhs, const f
   return true;
 }
 
+bool rbgs_tiled_refine_fits(int n)
+{
+  // the launch shape launch_in picks for the fused pass
+  using Sh = Shape<float, false, 2, kInProlong, 2>;
+  constexpr int W = Sh::W, RPW = Sh::RPW, PD = Sh::PD;
+  auto k64 = k_rbgs_tiled<float, false, 2, W, RPW, PD, kInProlong, 2, 64>;
+  LaunchShape L = shape_for<Tiled<float, false, 2, W, RPW, PD, 2, 64>>(n, resident_capacity(k64, 64 * W));
+  if constexpr (Sh::NARROW) {
+    auto k32 = k_rbgs_tiled<float, false, 2, W, RPW, PD, kInProlong, 2, 32>;
+    const LaunchShape L32 =
+        shape_for<Tiled<float, false, 2, W, RPW, PD, 2, 32>>(n, resident_capacity(k32, 64 * W));
+    if (L32.cost < L.cost) L = L32;
+  }
+  return L.blocks <= kStreamPartials;
+}
+
 void ir_scales_init(hipStream_t s, int n, const double* norm2, double scale0, double* ss)
 {
   const double interior = (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
