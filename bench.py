@@ -37,9 +37,9 @@ Also reported:
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fv] [--n 513]
 
 HBM traffic of the fine-level smoother (two counter runs, then a summary):
-  rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py --pmc-sample
-  rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o pmc -- python bench.py --pmc-sample
-  python bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d out/pmc_fetch -o pmc -- python bench.py --pmc-sample
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d out/pmc_write -o pmc -- python bench.py --pmc-sample
+  python bench.py --summarize-pmc out/pmc_fetch out/pmc_write
 --pmc-sample runs a plain device copy of 1 GiB (the calibration: its counters must read
 1 GiB fetched and 1 GiB written) and 10 launches of the fused FP64 smoother at 513^3.
 """

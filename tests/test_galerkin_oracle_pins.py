@@ -10,8 +10,8 @@ fixes independently of the oracle's products:
   - two-grid orthogonality: after an exact coarse-grid correction the restricted residual
     vanishes, R (f - A (u + P A_c^{-1} R r)) = 0;
   - the discrete solution is a fixed point of the V-cycle, and V-cycles on the lognormal
-    coefficient converge at a smaller factor than the rediscretised hierarchy's (survey: about
-    0.26 there), in fewer cycles than the C oracle needs.
+    coefficient converge at a smaller factor than the rediscretised hierarchy's (about 0.26
+    there), in fewer cycles than the C oracle needs.
 """
 import numpy as np
 import pytest
